@@ -1,0 +1,207 @@
+/*
+ * scrooge.h -- C ABI of libscrooge_hip.so: windowed GenASM pairwise alignment
+ * (Scrooge, arXiv 2208.09985) on AMD Instinct MI355X (gfx950).
+ *
+ * Problem (Section 2.1): given a text and a pattern over {A,C,G,T}, find the
+ * smallest number of substitutions, insertions and deletions turning the text
+ * into the pattern, and the edit sequence (CIGAR).  The method is GenASM-DC
+ * (Algorithm 1, Section 2.2.1) and GenASM-TB (Section 2.2.2) applied window
+ * by window (Section 2.2.3) with the three Scrooge improvements: stored
+ * entries instead of edges (Section 2.4.1), discarded entries that traceback
+ * never reads (Section 2.4.2) and early termination (Section 2.4.3).
+ *
+ * Conventions common to every call:
+ *   - Every function returns an int status (SCG_OK or a negative SCG_E*);
+ *     nothing aborts or throws across this boundary.  scg_strerror() names it.
+ *   - Sequences are ASCII A/C/G/T (either case).  Anything else is an input
+ *     error: host input is rejected at batch creation (SCG_EALPHABET); device
+ *     input marks the offending pair with SCG_PAIR_BAD_INPUT.
+ *   - Windows: 1 <= W <= 64, 0 <= O < W, 0 <= k <= W (else SCG_EINVAL).
+ *     Window w aligns pattern[p0, p0+m_w) with text[t0, t0+n_w), m_w =
+ *     min(W, m-p0), n_w = min(W, n-t0), allowing k_w = min(k, m_w) edits.
+ *     Traceback stops once W-O characters of text or pattern are consumed
+ *     (or the window's pattern is used up); the next window starts there.
+ *     Traceback prefers M, then S, then I, then D.  The text tail after the
+ *     last aligned character is free; text_end reports how much was consumed.
+ *   - Operations: SCG_OP_M '=' match, SCG_OP_S 'X' substitution, SCG_OP_I 'I'
+ *     a pattern character absent from the text, SCG_OP_D 'D' a text character
+ *     absent from the pattern.  edits = number of non-M operations.
+ *   - CIGAR output is run-length encoded as uint32 words (len << 2) | op,
+ *     runs merged across windows.  A pair of lengths (m, n) never needs more
+ *     than m + n + 1 words.
+ *   - Device pointers are used as-is on the caller's HIP stream (a
+ *     hipStream_t passed as void*; NULL = the null stream).  The library
+ *     owns only its own workspace; every caller buffer stays the caller's.
+ */
+#ifndef SCROOGE_H
+#define SCROOGE_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum {
+    SCG_OK = 0,
+    SCG_EINVAL = -1,      /* bad argument (NULL, size or W/O/k range)          */
+    SCG_EALPHABET = -2,   /* a character outside A/C/G/T (host input)          */
+    SCG_ERANGE = -3,      /* caller buffer too small                           */
+    SCG_ENOMEM = -4,      /* device or host allocation failed                  */
+    SCG_EDEVICE = -5,     /* a HIP runtime call failed                         */
+    SCG_ENOMODEL = -6,    /* learned mode requested without a loaded predictor */
+    SCG_EINTERNAL = -7    /* the device reported an inconsistent state         */
+};
+
+/* per-pair status values */
+enum {
+    SCG_PAIR_OK = 0,
+    SCG_PAIR_NOT_ALIGNED = 1,  /* some window had no distance <= k_w; edits = -1 */
+    SCG_PAIR_BAD_INPUT = 2,    /* non-ACGT character in device input             */
+    SCG_PAIR_ERROR = 3         /* internal inconsistency or run buffer overflow  */
+};
+
+enum { SCG_OP_M = 0, SCG_OP_S = 1, SCG_OP_I = 2, SCG_OP_D = 3 };
+
+/* how many error rows each window computes before falling back */
+enum {
+    SCG_MODE_PLAIN = 0,    /* every window computes all rows 0..k_w (with early termination)  */
+    SCG_MODE_LEARNED = 1,  /* the loaded predictor picks a row budget k' per window;           */
+                           /* a window with no distance <= k' is recomputed with all rows      */
+    SCG_MODE_FIXED = 2     /* constant budget (fixed_rows) per window, same fallback           */
+};
+
+enum { SCG_ORDER_INPUT = 0, SCG_ORDER_LONGEST_FIRST = 1 };
+enum { SCG_WHERE_HOST = 0, SCG_WHERE_DEVICE = 1 };
+enum { SCG_FLAG_GRAPH = 1 };  /* replay the batch's launches from a captured hipGraph */
+
+typedef struct {
+    int32_t W, O, k;        /* window size, overlap, edit budget per window            */
+    int32_t mode;           /* SCG_MODE_*                                              */
+    int32_t slots;          /* windows in flight per wavefront, 1..16 (0 = automatic)  */
+    int32_t waves_per_cu;   /* persistent wavefronts per CU (0 = occupancy maximum)    */
+    int32_t order;          /* SCG_ORDER_* : queue order of pairs                      */
+    int32_t fixed_rows;     /* SCG_MODE_FIXED: rows computed before falling back       */
+    float tau;              /* SCG_MODE_LEARNED: confidence needed for a smaller budget */
+    int32_t flags;          /* SCG_FLAG_*                                              */
+} scg_params;
+
+typedef struct {
+    double kernel_ms;          /* alignment kernel time of the last run (HIP events)     */
+    double pack_ms;            /* encode/pack kernel time of the last run                */
+    int64_t windows;           /* windows aligned                                        */
+    int64_t ops_alg;           /* sum over windows of (d_w+1) + 2 n_w + 7 n_w d_w        */
+    int64_t fallback_windows;  /* windows recomputed after missing their budget          */
+    int64_t lane_steps;        /* sum over passes of lanes x diagonal steps (work issued) */
+    int64_t rounds;            /* wavefront rounds (one DC pass each)                    */
+    int64_t rows_budgeted;     /* sum over window attempts of rows computed              */
+} scg_stats;
+
+typedef struct scg_ctx scg_ctx;
+typedef struct scg_batch scg_batch;
+
+/* Name of a status code (static string). */
+const char* scg_strerror(int code);
+
+/* Text of the last failing HIP runtime call on this thread ("" if none):
+ * the call and the runtime's message.  Static per-thread storage. */
+const char* scg_last_hip_error(void);
+
+/* Default parameters: W=64, O=24, k=64, plain mode, automatic launch shape. */
+void scg_params_default(scg_params* p);
+
+/* Create a context on HIP device `device`.  *out receives the context; the
+ * caller releases it with scg_destroy.  Errors: SCG_EINVAL, SCG_EDEVICE. */
+int scg_create(scg_ctx** out, int device);
+void scg_destroy(scg_ctx* ctx);
+
+/* Number of compute units of the context's device (for launch planning). */
+int scg_device_cus(const scg_ctx* ctx);
+
+/* Load the row-budget predictor used by SCG_MODE_LEARNED: a 2-layer MLP
+ * F -> H (ReLU) -> C over per-window features (scg_features), all FP16,
+ * host arrays, row-major: w1[F*H], b1[H], w2[H*C], b2[C].  Class c predicts
+ * "d_w fits in budget_rows[c] rows" (budget_rows: C increasing int32,
+ * the last >= 64).  F must be SCG_NFEATURES, H <= 64, C <= 16.
+ * Copied to the device; the host arrays stay the caller's. */
+enum { SCG_NFEATURES = 16 };
+int scg_set_model(scg_ctx* ctx, int32_t F, int32_t H, int32_t C,
+                  const uint16_t* w1, const uint16_t* b1, const uint16_t* w2, const uint16_t* b2,
+                  const int32_t* budget_rows);
+
+/* Prepare a batch of npairs (pattern, text) pairs for repeated alignment.
+ * pat/txt: concatenated ASCII bytes; pat_off/txt_off: npairs+1 int64 byte
+ * offsets, always in HOST memory.  where = SCG_WHERE_HOST (bytes in host
+ * memory, validated and copied to the device) or SCG_WHERE_DEVICE (bytes
+ * already in device memory, used in place: they must outlive the batch).
+ * The batch owns its workspace (2-bit planes, queue, counters); free it
+ * with scg_batch_destroy.  Errors: SCG_EINVAL, SCG_EALPHABET, SCG_ENOMEM,
+ * SCG_EDEVICE, SCG_ENOMODEL (learned mode without scg_set_model). */
+int scg_batch_create(scg_ctx* ctx, const scg_params* params, int32_t npairs,
+                     const void* pat, const int64_t* pat_off, const void* txt, const int64_t* txt_off,
+                     int32_t where, void* stream, scg_batch** out);
+void scg_batch_destroy(scg_batch* b);
+
+/* uint32 words the runs buffer of scg_batch_run needs, and the per-pair
+ * start offsets into it (npairs+1 int64, host memory). */
+int64_t scg_batch_runs_capacity(const scg_batch* b);
+int scg_batch_runs_offsets(const scg_batch* b, int64_t* out);
+
+/* Align the batch: encode+pack (Section 2.5's 2-bit encoding), then the
+ * persistent fused DC+TB kernel.  All outputs are DEVICE pointers of npairs
+ * int32 each, except runs (scg_batch_runs_capacity uint32 words, pair p at
+ * offset runs_offsets[p]).  Asynchronous on `stream`; the caller
+ * synchronises before reading.  Pairs with status != SCG_PAIR_OK have
+ * edits = text_end = -1 and n_runs = 0. */
+int scg_batch_run(scg_batch* b, void* stream, int32_t* edits, int32_t* text_end, int32_t* status,
+                  uint32_t* runs, int32_t* n_runs);
+
+/* Synchronise the batch's last run and read its counters and timings. */
+int scg_batch_stats(scg_batch* b, scg_stats* out);
+
+/* One pair in host memory (convenience; allocates and synchronises).
+ * cigar receives a NUL-terminated string ("12=1X3I..."); cap must cover it
+ * (SCG_ERANGE with *cigar_len = needed length otherwise). */
+int scg_align(scg_ctx* ctx, const char* pattern, int32_t m, const char* text, int32_t n,
+              int32_t W, int32_t O, int32_t k, int32_t* edits, int32_t* text_end,
+              char* cigar, int32_t cigar_cap, int32_t* cigar_len);
+
+/* Render run words as a CIGAR string (host memory). */
+int scg_runs_to_cigar(const uint32_t* runs, int32_t n_runs, char* cigar, int32_t cap, int32_t* len);
+
+/* ---- learned row budget: features and predictor training (device pointers) ----
+ *
+ * scg_features: for nwin windows given as (pair, p0, t0) int32 triples (device,
+ * 3*nwin) of a prepared batch, write SCG_NFEATURES uint16 counts per window
+ * (device, row-major nwin x 16): the number of aligned 4-mer matches between
+ * pattern[p0, p0+m_w) and text[t0+delta, ...) on each diagonal delta = -3..3
+ * (7 counts), the number of single-character matches on the same diagonals
+ * (7 counts), m_w and n_w.  prev_dw is not a feature: windows are scored
+ * independently so the same features serve training and inference. */
+int scg_features(scg_batch* b, int32_t nwin, const int32_t* windows, uint16_t* features, void* stream);
+
+/* Forward pass of the predictor on a batch (device pointers, FP16 storage,
+ * FP32 accumulation): x[B*F] features scaled to [0,1] as fp16, weights as in
+ * scg_set_model, logits[B*C] fp32 out, hidden[B*H] fp16 (post-ReLU) out.
+ * With labels (int32[B], class index) also per-sample softmax cross-entropy
+ * loss[B] fp32 and dlogits[B*C] fp32 = (softmax - onehot) / B. */
+int scg_mlp_forward(int32_t B, int32_t F, int32_t H, int32_t C, const uint16_t* x,
+                    const uint16_t* w1, const uint16_t* b1, const uint16_t* w2, const uint16_t* b2,
+                    float* logits, uint16_t* hidden, const int32_t* labels, float* loss, float* dlogits,
+                    void* stream);
+
+/* Backward pass: given x, hidden (from forward), w2 and dlogits, accumulate
+ * FP32 gradients gw1[F*H], gb1[H], gw2[H*C], gb2[C] (overwritten, not added). */
+int scg_mlp_backward(int32_t B, int32_t F, int32_t H, int32_t C, const uint16_t* x, const uint16_t* hidden,
+                     const uint16_t* w2, const float* dlogits,
+                     float* gw1, float* gb1, float* gw2, float* gb2, void* stream);
+
+/* Adam step on FP32 master weights p[n] with gradient g[n] and moments m, v
+ * (all device), writing the FP16 copy p16[n].  step is 1-based. */
+int scg_adam_step(int32_t n, float* p, const float* g, float* m, float* v, uint16_t* p16,
+                  float lr, float beta1, float beta2, float eps, int32_t step, void* stream);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* SCROOGE_H */

@@ -1,0 +1,210 @@
+"""Python interface over the C ABI: contexts, prepared batches, one-pair calls.
+
+PyTorch provides device memory and the stream; every alignment step runs in
+the library's HIP kernels.  Names follow include/scrooge.h.
+"""
+from __future__ import annotations
+
+import ctypes
+import dataclasses
+import os
+
+import numpy as np
+
+from . import _lib as L
+
+OP_CHARS = "=XID"
+
+
+def _ptr(x) -> ctypes.c_void_p:
+    """Raw pointer of a numpy array or torch tensor (None -> NULL)."""
+    if x is None:
+        return ctypes.c_void_p(0)
+    if isinstance(x, np.ndarray):
+        return ctypes.c_void_p(x.ctypes.data)
+    return ctypes.c_void_p(x.data_ptr())
+
+
+def _stream_ptr(stream) -> ctypes.c_void_p:
+    if stream is None:
+        import torch
+        stream = torch.cuda.current_stream()
+    return ctypes.c_void_p(stream.cuda_stream)
+
+
+def params(W=64, O=24, k=64, mode="plain", slots=0, waves_per_cu=0, order="input", fixed_rows=16, tau=0.9,
+           graph=False) -> L.Params:
+    p = L.Params()
+    L.load().scg_params_default(ctypes.byref(p))
+    p.W, p.O, p.k = W, O, k
+    p.mode = {"plain": L.MODE_PLAIN, "learned": L.MODE_LEARNED, "fixed": L.MODE_FIXED}[mode]
+    p.slots, p.waves_per_cu = slots, waves_per_cu
+    p.order = {"input": L.ORDER_INPUT, "longest_first": L.ORDER_LONGEST_FIRST}[order]
+    p.fixed_rows, p.tau = fixed_rows, tau
+    p.flags = L.FLAG_GRAPH if graph else 0
+    return p
+
+
+class Context:
+    """A device context (scg_create).  Holds the learned predictor, if any."""
+
+    def __init__(self, device: int = 0):
+        self._lib = L.load()
+        h = ctypes.c_void_p()
+        L.check(self._lib.scg_create(ctypes.byref(h), device), "scg_create")
+        self.handle = h
+        self.device = device
+
+    @property
+    def cus(self) -> int:
+        return self._lib.scg_device_cus(self.handle)
+
+    def set_model(self, w1, b1, w2, b2, budget_rows) -> None:
+        """fp16 arrays (numpy float16 or uint16 views) w1[F,H], b1[H], w2[H,C], b2[C]."""
+        arrs = [np.ascontiguousarray(np.asarray(a, dtype=np.float16)).view(np.uint16) for a in (w1, b1, w2, b2)]
+        F, H = arrs[0].shape
+        C = arrs[2].shape[1]
+        br = np.ascontiguousarray(budget_rows, dtype=np.int32)
+        L.check(self._lib.scg_set_model(self.handle, F, H, C, *[_ptr(a) for a in arrs], _ptr(br)), "scg_set_model")
+        self._model = (arrs, br)
+
+    def load_model(self, path: str) -> None:
+        z = np.load(path, allow_pickle=False)
+        self.set_model(z["w1"], z["b1"], z["w2"], z["b2"], z["budget_rows"])
+
+    def close(self) -> None:
+        if getattr(self, "handle", None):
+            self._lib.scg_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def align(self, pattern: bytes, text: bytes, W: int = 64, O: int = 24, k: int = 64):
+        """One pair in host memory (scg_align).  Returns (edits, text_end, cigar)."""
+        e, te, ln = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int32()
+        cap = 2 * (len(pattern) + len(text)) * 11 + 16
+        buf = ctypes.create_string_buffer(cap)
+        rc = self._lib.scg_align(self.handle, pattern, len(pattern), text, len(text), W, O, k,
+                                 ctypes.byref(e), ctypes.byref(te), buf, cap, ctypes.byref(ln))
+        L.check(rc, "scg_align")
+        return e.value, te.value, buf.value.decode()
+
+
+@dataclasses.dataclass
+class Result:
+    edits: object
+    text_end: object
+    status: object
+    runs: object
+    n_runs: object
+    runs_off: np.ndarray
+
+    def to_host(self) -> "Result":
+        def h(x):
+            return x.cpu().numpy() if hasattr(x, "cpu") else x
+        return Result(h(self.edits), h(self.text_end), h(self.status), h(self.runs), h(self.n_runs), self.runs_off)
+
+    def run_words(self, i: int) -> np.ndarray:
+        r = self.to_host() if hasattr(self.runs, "cpu") else self
+        s = int(r.runs_off[i])
+        return np.asarray(r.runs[s:s + int(r.n_runs[i])], dtype=np.uint32)
+
+    def ops(self, i: int) -> np.ndarray:
+        """Expanded op list (0..3) of pair i."""
+        w = self.run_words(i)
+        return np.repeat((w & 3).astype(np.uint8), (w >> 2).astype(np.int64))
+
+    def cigar(self, i: int) -> str:
+        return "".join(f"{int(x) >> 2}{OP_CHARS[int(x) & 3]}" for x in self.run_words(i))
+
+
+class Batch:
+    """A prepared batch (scg_batch_create) and its output buffers."""
+
+    def __init__(self, ctx: Context, batch, prm: L.Params | None = None, device_input: bool = True, stream=None):
+        import torch
+        self.ctx = ctx
+        self._lib = ctx._lib
+        self.prm = prm if prm is not None else params()
+        self.npairs = int(len(batch.pat_off) - 1)
+        self.dev = torch.device(f"cuda:{ctx.device}")
+        pat_off = np.ascontiguousarray(batch.pat_off, dtype=np.int64)
+        txt_off = np.ascontiguousarray(batch.txt_off, dtype=np.int64)
+        self._keep = [pat_off, txt_off]
+        if device_input:
+            pat = torch.from_numpy(np.ascontiguousarray(batch.pat)).to(self.dev)
+            txt = torch.from_numpy(np.ascontiguousarray(batch.txt)).to(self.dev)
+            torch.cuda.synchronize(self.dev)
+            self._keep += [pat, txt]
+            where = L.WHERE_DEVICE
+        else:
+            pat = np.ascontiguousarray(batch.pat)
+            txt = np.ascontiguousarray(batch.txt)
+            self._keep += [pat, txt]
+            where = L.WHERE_HOST
+        h = ctypes.c_void_p()
+        rc = self._lib.scg_batch_create(ctx.handle, ctypes.byref(self.prm), self.npairs, _ptr(pat), _ptr(pat_off),
+                                        _ptr(txt), _ptr(txt_off), where, _stream_ptr(stream), ctypes.byref(h))
+        L.check(rc, "scg_batch_create")
+        self.handle = h
+        cap = int(self._lib.scg_batch_runs_capacity(h))
+        self.runs_off = np.zeros(self.npairs + 1, np.int64)
+        L.check(self._lib.scg_batch_runs_offsets(h, _ptr(self.runs_off)), "scg_batch_runs_offsets")
+        n = max(self.npairs, 1)
+        self.edits = torch.empty(n, dtype=torch.int32, device=self.dev)
+        self.text_end = torch.empty(n, dtype=torch.int32, device=self.dev)
+        self.status = torch.empty(n, dtype=torch.int32, device=self.dev)
+        self.n_runs = torch.empty(n, dtype=torch.int32, device=self.dev)
+        self.runs = torch.empty(max(cap, 1), dtype=torch.int32, device=self.dev)
+
+    def run(self, stream=None) -> None:
+        rc = self._lib.scg_batch_run(self.handle, _stream_ptr(stream), _ptr(self.edits), _ptr(self.text_end),
+                                     _ptr(self.status), _ptr(self.runs), _ptr(self.n_runs))
+        L.check(rc, "scg_batch_run")
+
+    def stats(self) -> L.Stats:
+        st = L.Stats()
+        L.check(self._lib.scg_batch_stats(self.handle, ctypes.byref(st)), "scg_batch_stats")
+        return st
+
+    def result(self) -> Result:
+        n = self.npairs
+        return Result(self.edits[:n], self.text_end[:n], self.status[:n], self.runs.view(-1), self.n_runs[:n],
+                      self.runs_off).to_host()
+
+    def features(self, windows: np.ndarray, stream=None):
+        """Features (uint16 [nwin, 16]) of windows given as int32 [nwin, 3] (pair, p0, t0)."""
+        import torch
+        w = torch.from_numpy(np.ascontiguousarray(windows, dtype=np.int32)).to(self.dev)
+        out = torch.empty((max(len(windows), 1), L.NFEATURES), dtype=torch.int16, device=self.dev)
+        L.check(self._lib.scg_features(self.handle, len(windows), _ptr(w), _ptr(out), _stream_ptr(stream)),
+                "scg_features")
+        return out[:len(windows)]
+
+    def close(self) -> None:
+        if getattr(self, "handle", None):
+            self._lib.scg_batch_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def align_batch(ctx: Context, batch, W=64, O=24, k=64, mode="plain", **kw) -> Result:
+    """Prepare, run once and return host results (convenience)."""
+    import torch
+    b = Batch(ctx, batch, params(W=W, O=O, k=k, mode=mode, **kw))
+    b.run()
+    torch.cuda.synchronize(b.dev)
+    res = b.result()
+    st = b.stats()
+    b.close()
+    res.stats = st
+    return res

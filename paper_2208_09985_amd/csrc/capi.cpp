@@ -1,0 +1,546 @@
+// C ABI of libscrooge_hip.so (declarations and contracts: include/scrooge.h).
+//
+// Host responsibilities: argument validation, workspace management (2-bit
+// planes, queue, counters), queue order, launch shape, hipGraph capture of a
+// batch's launch sequence, and timing with HIP events.  Every step of the
+// alignment itself runs in the HIP kernels.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <numeric>
+#include <vector>
+
+#include "../../include/scrooge.h"
+#include "internal.h"
+
+struct scg_ctx {
+    int device = 0;
+    int num_cu = 0;
+    bool has_model = false;
+    int F = 0, H = 0, C = 0;
+    __half* model_d = nullptr;      // w1 | b1 | w2 | b2
+    int32_t* budget_d = nullptr;
+};
+
+struct scg_batch {
+    scg_ctx* ctx = nullptr;
+    scg_params p{};
+    int32_t npairs = 0;
+    // sequences (ASCII) on the device
+    uint8_t* pat_d = nullptr;
+    uint8_t* txt_d = nullptr;
+    bool own_seq = false;
+    int64_t* pat_off_d = nullptr;
+    int64_t* txt_off_d = nullptr;
+    // 2-bit planes
+    Plane2* pplanes = nullptr;
+    Plane2* tplanes = nullptr;
+    int64_t pwords = 0, twords = 0;
+    int64_t* pword_d = nullptr;
+    int64_t* tword_d = nullptr;
+    int32_t* plen_d = nullptr;
+    int32_t* tlen_d = nullptr;
+    uint8_t* bad_d = nullptr;
+    int32_t* order_d = nullptr;
+    int64_t* runs_off_d = nullptr;
+    std::vector<int64_t> runs_off_h;
+    uint32_t* queue_d = nullptr;
+    unsigned long long* stats_d = nullptr;
+    // launch shape
+    int ns = 1;
+    int grid = 1;
+    size_t lds = 0;
+    // timing
+    hipEvent_t ev[4] = {nullptr, nullptr, nullptr, nullptr};
+    bool timed = false;
+    // captured launch sequence
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t gexec = nullptr;
+    const void* gkey[6] = {nullptr, nullptr, nullptr, nullptr, nullptr, nullptr};
+};
+
+namespace {
+
+thread_local char g_last_error[256] = "";
+
+int from_hip(hipError_t e, const char* what = "HIP call") {
+    if (e == hipSuccess) return SCG_OK;
+    std::snprintf(g_last_error, sizeof g_last_error, "%s: %s (%d)", what, hipGetErrorString(e), (int)e);
+    if (e == hipErrorOutOfMemory) return SCG_ENOMEM;
+    return SCG_EDEVICE;
+}
+
+#define HIP_TRY(x)                                       \
+    do {                                                 \
+        hipError_t _e = (x);                             \
+        if (_e != hipSuccess) return from_hip(_e, #x);   \
+    } while (0)
+
+template <class T>
+int dev_alloc(T** p, size_t count) {
+    *p = nullptr;
+    if (count == 0) count = 1;
+    return from_hip(hipMalloc((void**)p, count * sizeof(T)));
+}
+
+bool valid_base(uint8_t c) {
+    switch (c | 0x20) {
+    case 'a': case 'c': case 'g': case 't': return true;
+    default: return false;
+    }
+}
+
+int check_params(const scg_params* p) {
+    if (!p) return SCG_EINVAL;
+    if (p->W < 1 || p->W > 64 || p->O < 0 || p->O >= p->W || p->k < 0 || p->k > p->W) return SCG_EINVAL;
+    if (p->mode < SCG_MODE_PLAIN || p->mode > SCG_MODE_FIXED) return SCG_EINVAL;
+    if (p->slots < 0 || p->slots > kMaxSlots || p->waves_per_cu < 0) return SCG_EINVAL;
+    if (p->order != SCG_ORDER_INPUT && p->order != SCG_ORDER_LONGEST_FIRST) return SCG_EINVAL;
+    if (p->mode == SCG_MODE_FIXED && (p->fixed_rows < 1 || p->fixed_rows > 64)) return SCG_EINVAL;
+    if (p->mode == SCG_MODE_LEARNED && !(p->tau > 0.f && p->tau <= 1.f)) return SCG_EINVAL;
+    return SCG_OK;
+}
+
+void free_batch(scg_batch* b) {
+    if (!b) return;
+    if (b->gexec) (void)hipGraphExecDestroy(b->gexec);
+    if (b->graph) (void)hipGraphDestroy(b->graph);
+    for (auto& e : b->ev)
+        if (e) (void)hipEventDestroy(e);
+    void* ptrs[] = {b->own_seq ? b->pat_d : nullptr, b->own_seq ? b->txt_d : nullptr, b->pat_off_d, b->txt_off_d,
+                    b->pplanes, b->tplanes, b->pword_d, b->tword_d, b->plen_d, b->tlen_d, b->bad_d, b->order_d,
+                    b->runs_off_d, b->queue_d, b->stats_d};
+    for (void* q : ptrs)
+        if (q) (void)hipFree(q);
+    delete b;
+}
+
+int enqueue_run(scg_batch* b, hipStream_t s, int32_t* edits, int32_t* text_end, int32_t* status, uint32_t* runs,
+                int32_t* n_runs, bool with_events) {
+    const scg_ctx* c = b->ctx;
+    if (with_events) HIP_TRY(hipEventRecord(b->ev[0], s));
+    HIP_TRY(launch_reset(b->queue_d, b->stats_d, b->bad_d, b->npairs, s));
+    HIP_TRY(launch_pack(b->pat_d, b->pat_off_d, b->pword_d, b->npairs, b->pwords, b->pplanes, b->bad_d, c->num_cu, s));
+    HIP_TRY(launch_pack(b->txt_d, b->txt_off_d, b->tword_d, b->npairs, b->twords, b->tplanes, b->bad_d, c->num_cu, s));
+    if (with_events) HIP_TRY(hipEventRecord(b->ev[1], s));
+    AlignArgs a{};
+    a.pplanes = b->pplanes;
+    a.tplanes = b->tplanes;
+    a.pword = b->pword_d;
+    a.tword = b->tword_d;
+    a.plen = b->plen_d;
+    a.tlen = b->tlen_d;
+    a.bad = b->bad_d;
+    a.order = b->order_d;
+    a.npairs = b->npairs;
+    a.W = b->p.W;
+    a.O = b->p.O;
+    a.k = b->p.k;
+    a.cap = b->p.W - b->p.O;
+    a.mode = b->p.mode;
+    a.fixed_rows = b->p.fixed_rows;
+    a.ns = b->ns;
+    a.ccols = a.cap + 1;
+    if (b->p.mode == SCG_MODE_LEARNED) {
+        const int F = c->F, H = c->H, C = c->C;
+        a.model.w1 = c->model_d;
+        a.model.b1 = c->model_d + F * H;
+        a.model.w2 = c->model_d + F * H + H;
+        a.model.b2 = c->model_d + F * H + H + H * C;
+        a.model.budget_rows = c->budget_d;
+        a.model.H = H;
+        a.model.C = C;
+        a.model.tau = b->p.tau;
+    }
+    a.edits = edits;
+    a.text_end = text_end;
+    a.status = status;
+    a.runs = runs;
+    a.runs_off = b->runs_off_d;
+    a.n_runs = n_runs;
+    a.queue = b->queue_d;
+    a.stats = b->stats_d;
+    if (b->npairs > 0) HIP_TRY(launch_align(a, b->grid, b->lds, s));
+    if (with_events) HIP_TRY(hipEventRecord(b->ev[2], s));
+    return SCG_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* scg_strerror(int code) {
+    switch (code) {
+    case SCG_OK: return "ok";
+    case SCG_EINVAL: return "invalid argument";
+    case SCG_EALPHABET: return "character outside A/C/G/T";
+    case SCG_ERANGE: return "buffer too small";
+    case SCG_ENOMEM: return "out of memory";
+    case SCG_EDEVICE: return "HIP runtime error";
+    case SCG_ENOMODEL: return "no predictor loaded";
+    case SCG_EINTERNAL: return "internal inconsistency";
+    default: return "unknown status";
+    }
+}
+
+const char* scg_last_hip_error(void) { return g_last_error; }
+
+void scg_params_default(scg_params* p) {
+    if (!p) return;
+    std::memset(p, 0, sizeof(*p));
+    p->W = 64;
+    p->O = 24;
+    p->k = 64;
+    p->mode = SCG_MODE_PLAIN;
+    p->order = SCG_ORDER_INPUT;
+    p->fixed_rows = 16;
+    p->tau = 0.9f;
+}
+
+int scg_create(scg_ctx** out, int device) {
+    if (!out) return SCG_EINVAL;
+    *out = nullptr;
+    int n = 0;
+    HIP_TRY(hipGetDeviceCount(&n));
+    if (device < 0 || device >= n) return SCG_EINVAL;
+    HIP_TRY(hipSetDevice(device));
+    hipDeviceProp_t prop;
+    HIP_TRY(hipGetDeviceProperties(&prop, device));
+    scg_ctx* c = new (std::nothrow) scg_ctx();
+    if (!c) return SCG_ENOMEM;
+    c->device = device;
+    c->num_cu = prop.multiProcessorCount;
+    *out = c;
+    return SCG_OK;
+}
+
+void scg_destroy(scg_ctx* c) {
+    if (!c) return;
+    if (c->model_d) (void)hipFree(c->model_d);
+    if (c->budget_d) (void)hipFree(c->budget_d);
+    delete c;
+}
+
+int scg_device_cus(const scg_ctx* c) { return c ? c->num_cu : 0; }
+
+int scg_set_model(scg_ctx* c, int32_t F, int32_t H, int32_t C, const uint16_t* w1, const uint16_t* b1,
+                  const uint16_t* w2, const uint16_t* b2, const int32_t* budget_rows) {
+    if (!c || !w1 || !b1 || !w2 || !b2 || !budget_rows) return SCG_EINVAL;
+    if (F != kFeatures || H < 1 || H > kMaxHidden || C < 1 || C > 4) return SCG_EINVAL;
+    for (int i = 0; i < C; ++i) {
+        if (budget_rows[i] < 1 || budget_rows[i] > 64) return SCG_EINVAL;
+        if (i > 0 && budget_rows[i] <= budget_rows[i - 1]) return SCG_EINVAL;
+    }
+    if (budget_rows[C - 1] < 64) return SCG_EINVAL;
+    HIP_TRY(hipSetDevice(c->device));
+    const size_t n = (size_t)F * H + H + (size_t)H * C + C;
+    std::vector<uint16_t> blob(n);
+    std::memcpy(blob.data(), w1, sizeof(uint16_t) * F * H);
+    std::memcpy(blob.data() + F * H, b1, sizeof(uint16_t) * H);
+    std::memcpy(blob.data() + F * H + H, w2, sizeof(uint16_t) * H * C);
+    std::memcpy(blob.data() + F * H + H + H * C, b2, sizeof(uint16_t) * C);
+    if (c->model_d) (void)hipFree(c->model_d);
+    if (c->budget_d) (void)hipFree(c->budget_d);
+    c->model_d = nullptr;
+    c->budget_d = nullptr;
+    c->has_model = false;
+    int rc = dev_alloc(&c->model_d, n);
+    if (rc) return rc;
+    rc = dev_alloc(&c->budget_d, (size_t)C);
+    if (rc) return rc;
+    HIP_TRY(hipMemcpy(c->model_d, blob.data(), n * sizeof(uint16_t), hipMemcpyHostToDevice));
+    HIP_TRY(hipMemcpy(c->budget_d, budget_rows, C * sizeof(int32_t), hipMemcpyHostToDevice));
+    c->F = F;
+    c->H = H;
+    c->C = C;
+    c->has_model = true;
+    return SCG_OK;
+}
+
+int scg_batch_create(scg_ctx* c, const scg_params* params, int32_t npairs, const void* pat, const int64_t* pat_off,
+                     const void* txt, const int64_t* txt_off, int32_t where, void* stream, scg_batch** out) {
+    if (!out) return SCG_EINVAL;
+    *out = nullptr;
+    if (!c || npairs < 0 || !pat_off || !txt_off) return SCG_EINVAL;
+    if (where != SCG_WHERE_HOST && where != SCG_WHERE_DEVICE) return SCG_EINVAL;
+    int rc = check_params(params);
+    if (rc) return rc;
+    if (params->mode == SCG_MODE_LEARNED && !c->has_model) return SCG_ENOMODEL;
+    if (pat_off[0] != 0 || txt_off[0] != 0) return SCG_EINVAL;
+    for (int32_t i = 0; i < npairs; ++i) {
+        const int64_t m = pat_off[i + 1] - pat_off[i], n = txt_off[i + 1] - txt_off[i];
+        if (m < 0 || n < 0 || m > (1 << 30) || n > (1 << 30)) return SCG_EINVAL;
+    }
+    const int64_t pbytes = pat_off[npairs], tbytes = txt_off[npairs];
+    if ((pbytes > 0 && !pat) || (tbytes > 0 && !txt)) return SCG_EINVAL;
+    if (where == SCG_WHERE_HOST) {
+        const uint8_t* ps = (const uint8_t*)pat;
+        const uint8_t* ts = (const uint8_t*)txt;
+        for (int64_t i = 0; i < pbytes; ++i)
+            if (!valid_base(ps[i])) return SCG_EALPHABET;
+        for (int64_t i = 0; i < tbytes; ++i)
+            if (!valid_base(ts[i])) return SCG_EALPHABET;
+    }
+    HIP_TRY(hipSetDevice(c->device));
+    hipStream_t s = (hipStream_t)stream;
+    scg_batch* b = new (std::nothrow) scg_batch();
+    if (!b) return SCG_ENOMEM;
+    b->ctx = c;
+    b->p = *params;
+    b->npairs = npairs;
+    // host-side tables
+    std::vector<int64_t> pw(npairs + 1), tw(npairs + 1);
+    std::vector<int32_t> pl(npairs), tl(npairs);
+    b->runs_off_h.assign(npairs + 1, 0);
+    pw[0] = tw[0] = 0;
+    for (int32_t i = 0; i < npairs; ++i) {
+        pl[i] = (int32_t)(pat_off[i + 1] - pat_off[i]);
+        tl[i] = (int32_t)(txt_off[i + 1] - txt_off[i]);
+        pw[i + 1] = pw[i] + (pl[i] + 63) / 64 + 1;   // + one padding Plane2
+        tw[i + 1] = tw[i] + (tl[i] + 63) / 64 + 1;
+        b->runs_off_h[i + 1] = b->runs_off_h[i] + pl[i] + tl[i] + 1;
+    }
+    b->pwords = pw[npairs];
+    b->twords = tw[npairs];
+    std::vector<int32_t> order(npairs);
+    std::iota(order.begin(), order.end(), 0);
+    if (params->order == SCG_ORDER_LONGEST_FIRST)
+        std::stable_sort(order.begin(), order.end(),
+                         [&](int32_t x, int32_t y) { return (int64_t)pl[x] + tl[x] > (int64_t)pl[y] + tl[y]; });
+    // device workspace
+    auto fail = [&](int code) {
+        free_batch(b);
+        return code;
+    };
+    if ((rc = dev_alloc(&b->pat_off_d, npairs + 1)) || (rc = dev_alloc(&b->txt_off_d, npairs + 1)) ||
+        (rc = dev_alloc(&b->pplanes, (size_t)b->pwords)) || (rc = dev_alloc(&b->tplanes, (size_t)b->twords)) ||
+        (rc = dev_alloc(&b->pword_d, npairs + 1)) || (rc = dev_alloc(&b->tword_d, npairs + 1)) ||
+        (rc = dev_alloc(&b->plen_d, npairs)) || (rc = dev_alloc(&b->tlen_d, npairs)) ||
+        (rc = dev_alloc(&b->bad_d, npairs)) || (rc = dev_alloc(&b->order_d, npairs)) ||
+        (rc = dev_alloc(&b->runs_off_d, npairs + 1)) || (rc = dev_alloc(&b->queue_d, 1)) ||
+        (rc = dev_alloc(&b->stats_d, ST_COUNT)))
+        return fail(rc);
+    if (where == SCG_WHERE_HOST) {
+        b->own_seq = true;
+        if ((rc = dev_alloc(&b->pat_d, (size_t)pbytes)) || (rc = dev_alloc(&b->txt_d, (size_t)tbytes))) return fail(rc);
+        if (pbytes && (rc = from_hip(hipMemcpyAsync(b->pat_d, pat, pbytes, hipMemcpyHostToDevice, s)))) return fail(rc);
+        if (tbytes && (rc = from_hip(hipMemcpyAsync(b->txt_d, txt, tbytes, hipMemcpyHostToDevice, s)))) return fail(rc);
+    } else {
+        b->pat_d = (uint8_t*)pat;
+        b->txt_d = (uint8_t*)txt;
+    }
+    struct Up {
+        void* dst;
+        const void* src;
+        size_t bytes;
+    } ups[] = {{b->pat_off_d, pat_off, sizeof(int64_t) * (npairs + 1)},
+               {b->txt_off_d, txt_off, sizeof(int64_t) * (npairs + 1)},
+               {b->pword_d, pw.data(), sizeof(int64_t) * (npairs + 1)},
+               {b->tword_d, tw.data(), sizeof(int64_t) * (npairs + 1)},
+               {b->plen_d, pl.data(), sizeof(int32_t) * npairs},
+               {b->tlen_d, tl.data(), sizeof(int32_t) * npairs},
+               {b->order_d, order.data(), sizeof(int32_t) * npairs},
+               {b->runs_off_d, b->runs_off_h.data(), sizeof(int64_t) * (npairs + 1)}};
+    for (auto& u : ups)
+        if (u.bytes && (rc = from_hip(hipMemcpyAsync(u.dst, u.src, u.bytes, hipMemcpyHostToDevice, s)))) return fail(rc);
+    // host vectors die at return: wait for the copies
+    if ((rc = from_hip(hipStreamSynchronize(s)))) return fail(rc);
+    // launch shape
+    b->ns = params->slots > 0 ? params->slots : (params->mode == SCG_MODE_PLAIN ? 1 : 8);
+    b->lds = align_lds_bytes(params->W - params->O + 1, b->ns);
+    int per_cu = align_max_blocks_per_cu(b->lds);
+    if (params->waves_per_cu > 0) per_cu = std::min(per_cu, params->waves_per_cu);
+    b->grid = std::max(1, per_cu * c->num_cu);
+    const int64_t need = (npairs + b->ns - 1) / b->ns;   // more wavefronts than slots-worth of pairs idle
+    if (b->grid > need) b->grid = (int)std::max<int64_t>(1, need);
+    for (auto& e : b->ev)
+        if ((rc = from_hip(hipEventCreate(&e)))) return fail(rc);
+    *out = b;
+    return SCG_OK;
+}
+
+void scg_batch_destroy(scg_batch* b) {
+    if (b) (void)hipSetDevice(b->ctx->device);
+    free_batch(b);
+}
+
+int64_t scg_batch_runs_capacity(const scg_batch* b) { return b ? b->runs_off_h.back() : -1; }
+
+int scg_batch_runs_offsets(const scg_batch* b, int64_t* out) {
+    if (!b || !out) return SCG_EINVAL;
+    std::memcpy(out, b->runs_off_h.data(), sizeof(int64_t) * b->runs_off_h.size());
+    return SCG_OK;
+}
+
+int scg_batch_run(scg_batch* b, void* stream, int32_t* edits, int32_t* text_end, int32_t* status, uint32_t* runs,
+                  int32_t* n_runs) {
+    if (!b) return SCG_EINVAL;
+    if (b->npairs > 0 && (!edits || !text_end || !status || !runs || !n_runs)) return SCG_EINVAL;
+    HIP_TRY(hipSetDevice(b->ctx->device));
+    hipStream_t s = (hipStream_t)stream;
+    if (!(b->p.flags & SCG_FLAG_GRAPH)) {
+        b->timed = true;
+        return enqueue_run(b, s, edits, text_end, status, runs, n_runs, true);
+    }
+    const void* key[6] = {edits, text_end, status, runs, n_runs, nullptr};
+    bool same = b->gexec != nullptr;
+    for (int i = 0; i < 6 && same; ++i) same = key[i] == b->gkey[i];
+    if (!same) {
+        if (b->gexec) (void)hipGraphExecDestroy(b->gexec);
+        if (b->graph) (void)hipGraphDestroy(b->graph);
+        b->gexec = nullptr;
+        b->graph = nullptr;
+        hipStream_t cs;
+        HIP_TRY(hipStreamCreateWithFlags(&cs, hipStreamNonBlocking));
+        hipError_t e = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal);
+        int rc = e == hipSuccess ? enqueue_run(b, cs, edits, text_end, status, runs, n_runs, false) : from_hip(e);
+        hipGraph_t g = nullptr;
+        hipError_t e2 = hipStreamEndCapture(cs, &g);
+        (void)hipStreamDestroy(cs);
+        if (rc) {
+            if (g) (void)hipGraphDestroy(g);
+            return rc;
+        }
+        HIP_TRY(e2);
+        b->graph = g;
+        HIP_TRY(hipGraphInstantiate(&b->gexec, g, nullptr, nullptr, 0));
+        for (int i = 0; i < 6; ++i) b->gkey[i] = key[i];
+    }
+    b->timed = true;
+    HIP_TRY(hipEventRecord(b->ev[0], s));
+    HIP_TRY(hipGraphLaunch(b->gexec, s));
+    HIP_TRY(hipEventRecord(b->ev[2], s));
+    return SCG_OK;
+}
+
+int scg_batch_stats(scg_batch* b, scg_stats* out) {
+    if (!b || !out) return SCG_EINVAL;
+    std::memset(out, 0, sizeof(*out));
+    HIP_TRY(hipSetDevice(b->ctx->device));
+    if (!b->timed) return SCG_OK;
+    HIP_TRY(hipEventSynchronize(b->ev[2]));
+    unsigned long long st[ST_COUNT];
+    HIP_TRY(hipMemcpy(st, b->stats_d, sizeof(st), hipMemcpyDeviceToHost));
+    float total = 0.f, pack = 0.f;
+    HIP_TRY(hipEventElapsedTime(&total, b->ev[0], b->ev[2]));
+    if (!(b->p.flags & SCG_FLAG_GRAPH)) {
+        HIP_TRY(hipEventElapsedTime(&pack, b->ev[0], b->ev[1]));
+        out->kernel_ms = total - pack;
+        out->pack_ms = pack;
+    } else {
+        out->kernel_ms = total;
+        out->pack_ms = 0.0;
+    }
+    out->windows = (int64_t)st[ST_WINDOWS];
+    out->ops_alg = (int64_t)st[ST_OPS_ALG];
+    out->fallback_windows = (int64_t)st[ST_FALLBACK];
+    out->lane_steps = (int64_t)st[ST_LANE_STEPS];
+    out->rounds = (int64_t)st[ST_ROUNDS];
+    out->rows_budgeted = (int64_t)st[ST_ROWS];
+    if (st[ST_ERRORS]) return SCG_EINTERNAL;
+    return SCG_OK;
+}
+
+int scg_runs_to_cigar(const uint32_t* runs, int32_t n_runs, char* cigar, int32_t cap, int32_t* len) {
+    if ((!runs && n_runs > 0) || n_runs < 0 || !len || (!cigar && cap > 0)) return SCG_EINVAL;
+    static const char sym[4] = {'=', 'X', 'I', 'D'};
+    int64_t need = 0;
+    char tmp[16];
+    for (int32_t i = 0; i < n_runs; ++i) need += std::snprintf(tmp, sizeof tmp, "%u%c", runs[i] >> 2, sym[runs[i] & 3]);
+    *len = (int32_t)need;
+    if (need + 1 > cap) return SCG_ERANGE;
+    int64_t at = 0;
+    for (int32_t i = 0; i < n_runs; ++i)
+        at += std::snprintf(cigar + at, (size_t)(cap - at), "%u%c", runs[i] >> 2, sym[runs[i] & 3]);
+    cigar[at] = '\0';
+    return SCG_OK;
+}
+
+int scg_align(scg_ctx* c, const char* pattern, int32_t m, const char* text, int32_t n, int32_t W, int32_t O, int32_t k,
+              int32_t* edits, int32_t* text_end, char* cigar, int32_t cigar_cap, int32_t* cigar_len) {
+    if (!c || m < 0 || n < 0 || (m > 0 && !pattern) || (n > 0 && !text) || !edits || !text_end || !cigar_len)
+        return SCG_EINVAL;
+    scg_params p;
+    scg_params_default(&p);
+    p.W = W;
+    p.O = O;
+    p.k = k;
+    const int64_t po[2] = {0, m}, to[2] = {0, n};
+    scg_batch* b = nullptr;
+    int rc = scg_batch_create(c, &p, 1, pattern, po, text, to, SCG_WHERE_HOST, nullptr, &b);
+    if (rc) return rc;
+    const int64_t cap = scg_batch_runs_capacity(b);
+    int32_t* outs = nullptr;
+    uint32_t* runs_d = nullptr;
+    if ((rc = dev_alloc(&outs, 4)) || (rc = dev_alloc(&runs_d, (size_t)cap))) {
+        if (outs) (void)hipFree(outs);
+        scg_batch_destroy(b);
+        return rc;
+    }
+    rc = scg_batch_run(b, nullptr, outs, outs + 1, outs + 2, runs_d, outs + 3);
+    int32_t h[4] = {0, 0, 0, 0};
+    std::vector<uint32_t> runs;
+    if (!rc) rc = from_hip(hipMemcpy(h, outs, sizeof(h), hipMemcpyDeviceToHost));
+    if (!rc) {
+        runs.resize(std::max(0, h[3]));
+        if (h[3] > 0) rc = from_hip(hipMemcpy(runs.data(), runs_d, sizeof(uint32_t) * h[3], hipMemcpyDeviceToHost));
+    }
+    (void)hipFree(outs);
+    (void)hipFree(runs_d);
+    scg_batch_destroy(b);
+    if (rc) return rc;
+    *edits = h[0];
+    *text_end = h[1];
+    if (h[2] == SCG_PAIR_ERROR) return SCG_EINTERNAL;
+    return scg_runs_to_cigar(runs.data(), (int32_t)runs.size(), cigar, cigar_cap, cigar_len);
+}
+
+int scg_features(scg_batch* b, int32_t nwin, const int32_t* windows, uint16_t* features, void* stream) {
+    if (!b || nwin < 0 || (nwin > 0 && (!windows || !features))) return SCG_EINVAL;
+    HIP_TRY(hipSetDevice(b->ctx->device));
+    hipStream_t s = (hipStream_t)stream;
+    // planes are produced by the pack step of a run; make sure they exist
+    HIP_TRY(launch_reset(b->queue_d, b->stats_d, b->bad_d, b->npairs, s));
+    HIP_TRY(launch_pack(b->pat_d, b->pat_off_d, b->pword_d, b->npairs, b->pwords, b->pplanes, b->bad_d,
+                        b->ctx->num_cu, s));
+    HIP_TRY(launch_pack(b->txt_d, b->txt_off_d, b->tword_d, b->npairs, b->twords, b->tplanes, b->bad_d,
+                        b->ctx->num_cu, s));
+    HIP_TRY(launch_features(b->pplanes, b->tplanes, b->pword_d, b->tword_d, b->plen_d, b->tlen_d, b->npairs, b->p.W,
+                            nwin, windows, features, s));
+    return SCG_OK;
+}
+
+int scg_mlp_forward(int32_t B, int32_t F, int32_t H, int32_t C, const uint16_t* x, const uint16_t* w1,
+                    const uint16_t* b1, const uint16_t* w2, const uint16_t* b2, float* logits, uint16_t* hidden,
+                    const int32_t* labels, float* loss, float* dlogits, void* stream) {
+    if (B < 0 || F != kFeatures || H < 1 || H > kMaxHidden || C < 1 || C > 4) return SCG_EINVAL;
+    if (B > 0 && (!x || !w1 || !b1 || !w2 || !b2 || !logits || !hidden)) return SCG_EINVAL;
+    if (labels && (!loss || !dlogits)) return SCG_EINVAL;
+    HIP_TRY(launch_mlp_forward(B, F, H, C, (const __half*)x, (const __half*)w1, (const __half*)b1,
+                               (const __half*)w2, (const __half*)b2, logits, (__half*)hidden, labels, loss, dlogits,
+                               (hipStream_t)stream));
+    return SCG_OK;
+}
+
+int scg_mlp_backward(int32_t B, int32_t F, int32_t H, int32_t C, const uint16_t* x, const uint16_t* hidden,
+                     const uint16_t* w2, const float* dlogits, float* gw1, float* gb1, float* gw2, float* gb2,
+                     void* stream) {
+    if (B < 0 || F != kFeatures || H < 1 || H > kMaxHidden || C < 1 || C > 4) return SCG_EINVAL;
+    if (!gw1 || !gb1 || !gw2 || !gb2) return SCG_EINVAL;
+    if (B > 0 && (!x || !hidden || !w2 || !dlogits)) return SCG_EINVAL;
+    HIP_TRY(launch_mlp_backward(B, F, H, C, (const __half*)x, (const __half*)hidden, (const __half*)w2, dlogits,
+                                gw1, gb1, gw2, gb2, (hipStream_t)stream));
+    return SCG_OK;
+}
+
+int scg_adam_step(int32_t n, float* p, const float* g, float* m, float* v, uint16_t* p16, float lr, float beta1,
+                  float beta2, float eps, int32_t step, void* stream) {
+    if (n < 0 || step < 1 || (n > 0 && (!p || !g || !m || !v || !p16))) return SCG_EINVAL;
+    HIP_TRY(launch_adam(n, p, g, m, v, (__half*)p16, lr, beta1, beta2, eps, step, (hipStream_t)stream));
+    return SCG_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,87 @@
+// Internal definitions shared by the HIP kernels and the C-ABI layer of
+// libscrooge_hip.so.  Not part of the public interface (include/scrooge.h).
+#pragma once
+
+#include <hip/hip_fp16.h>
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+// 64 bases in planar 2-bit form: bit t of `lo` / `hi` is the low / high bit
+// of the code of base t (A=0, C=1, G=2, T=3).  Every sequence starts on a
+// Plane2 boundary and is followed by one zero padding Plane2, so a 64-base
+// window at any position inside the sequence reads two consecutive Plane2.
+struct Plane2 {
+    uint64_t lo, hi;
+};
+
+enum {
+    ST_WINDOWS = 0,
+    ST_OPS_ALG,
+    ST_FALLBACK,
+    ST_LANE_STEPS,
+    ST_ROUNDS,
+    ST_ROWS,
+    ST_ERRORS,
+    ST_COUNT = 8
+};
+
+constexpr int kMaxSlots = 16;     // windows in flight per wavefront
+constexpr int kMaxClasses = 16;   // predictor classes
+constexpr int kMaxHidden = 64;
+constexpr int kFeatures = 16;
+
+struct ModelDev {
+    const __half* w1;   // [F][H]
+    const __half* b1;   // [H]
+    const __half* w2;   // [H][C]
+    const __half* b2;   // [C]
+    const int32_t* budget_rows;  // [C]
+    int32_t H, C;
+    float tau;
+};
+
+struct AlignArgs {
+    const Plane2* pplanes;
+    const Plane2* tplanes;
+    const int64_t* pword;   // first Plane2 of each pattern
+    const int64_t* tword;   // first Plane2 of each text
+    const int32_t* plen;
+    const int32_t* tlen;
+    const uint8_t* bad;     // nonzero: the pair's input held a non-ACGT byte
+    const int32_t* order;   // queue order (pair indices)
+    int32_t npairs;
+    int32_t W, O, k, cap;   // cap = W - O: characters consumed per window
+    int32_t mode, fixed_rows;
+    int32_t ns;             // slots (windows in flight) per wavefront
+    int32_t ccols;          // stored columns of the traceback region = cap + 1
+    ModelDev model;
+    int32_t* edits;
+    int32_t* text_end;
+    int32_t* status;
+    uint32_t* runs;
+    const int64_t* runs_off;
+    int32_t* n_runs;
+    uint32_t* queue;              // [0]: next queue position
+    unsigned long long* stats;    // ST_COUNT counters
+};
+
+// launchers (defined in the .hip files)
+hipError_t launch_reset(uint32_t* queue, unsigned long long* stats, uint8_t* bad, int32_t npairs,
+                        hipStream_t s);
+hipError_t launch_pack(const uint8_t* seq, const int64_t* off, const int64_t* wordoff, int32_t npairs,
+                       int64_t total_words, Plane2* out, uint8_t* bad, int num_cu, hipStream_t s);
+hipError_t launch_align(const AlignArgs& a, int grid, size_t lds_bytes, hipStream_t s);
+size_t align_lds_bytes(int ccols, int ns);
+int align_max_blocks_per_cu(size_t lds_bytes);
+hipError_t launch_features(const Plane2* pplanes, const Plane2* tplanes, const int64_t* pword,
+                           const int64_t* tword, const int32_t* plen, const int32_t* tlen, int32_t npairs,
+                           int32_t W, int32_t nwin, const int32_t* windows, uint16_t* features, hipStream_t s);
+hipError_t launch_mlp_forward(int32_t B, int32_t F, int32_t H, int32_t C, const __half* x, const __half* w1,
+                              const __half* b1, const __half* w2, const __half* b2, float* logits,
+                              __half* hidden, const int32_t* labels, float* loss, float* dlogits,
+                              hipStream_t s);
+hipError_t launch_mlp_backward(int32_t B, int32_t F, int32_t H, int32_t C, const __half* x,
+                               const __half* hidden, const __half* w2, const float* dlogits, float* gw1,
+                               float* gb1, float* gw2, float* gb2, hipStream_t s);
+hipError_t launch_adam(int32_t n, float* p, const float* g, float* m, float* v, __half* p16, float lr,
+                       float b1, float b2, float eps, int32_t step, hipStream_t s);

@@ -1,0 +1,82 @@
+// Encode + pack: ASCII sequences to the planar 2-bit layout (Plane2).
+//
+// The paper's implementations convert each pair to a two-bit-per-base
+// encoding before alignment (Section 2.5).  Here one wavefront produces one
+// Plane2 (64 bases): lane t loads byte t of the slice (one coalesced 64-byte
+// read), and two ballots over the code bits are exactly the low and high bit
+// planes.  Lane 0 stores the 16-byte result.  The workload is a single pass
+// over the input bytes, so it is bound by HBM bandwidth.
+#include "internal.h"
+
+namespace {
+
+__global__ __launch_bounds__(256) void reset_kernel(uint32_t* queue, unsigned long long* stats, uint8_t* bad,
+                                                    int32_t npairs) {
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t == 0) queue[0] = 0;
+    if (t < ST_COUNT) stats[t] = 0;
+    for (int64_t x = t; x < npairs; x += (int64_t)gridDim.x * blockDim.x) bad[x] = 0;
+}
+
+__device__ __forceinline__ int base_code(uint32_t c, bool& bad) {
+    switch (c | 0x20u) {  // fold to lower case
+    case 'a': return 0;
+    case 'c': return 1;
+    case 'g': return 2;
+    case 't': return 3;
+    default: bad = true; return 0;
+    }
+}
+
+__global__ __launch_bounds__(256) void pack_kernel(const uint8_t* __restrict__ seq, const int64_t* __restrict__ off,
+                                                   const int64_t* __restrict__ wordoff, int32_t npairs,
+                                                   int64_t total_words, Plane2* __restrict__ out,
+                                                   uint8_t* __restrict__ bad) {
+    const int lane = threadIdx.x & 63;
+    const int64_t waves = (int64_t)gridDim.x * (blockDim.x >> 6);
+    int64_t w = (int64_t)blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
+    w = __builtin_amdgcn_readfirstlane((int)w);  // wave index is uniform (< 2^31 words)
+    for (; w < total_words; w += waves) {
+        // sequence s owning Plane2 w: the largest s with wordoff[s] <= w
+        int lo = 0, hi = npairs;
+        while (hi - lo > 1) {
+            const int mid = (lo + hi) >> 1;
+            if (wordoff[mid] <= w) lo = mid; else hi = mid;
+        }
+        const int64_t q = w - wordoff[lo];
+        const int64_t start = off[lo];
+        const int64_t len = off[lo + 1] - start;
+        const int64_t pos = q * 64 + lane;
+        bool badc = false;
+        int code = 0;
+        if (pos < len) code = base_code(seq[start + pos], badc);
+        const uint64_t plo = __ballot(code & 1);
+        const uint64_t phi = __ballot(code >> 1);
+        const uint64_t pbad = __ballot(badc);
+        if (lane == 0) {
+            out[w] = Plane2{plo, phi};
+            if (pbad) bad[lo] = 1;
+        }
+    }
+}
+
+}  // namespace
+
+hipError_t launch_reset(uint32_t* queue, unsigned long long* stats, uint8_t* bad, int32_t npairs, hipStream_t s) {
+    int blocks = (int)((npairs + 255) / 256);
+    if (blocks < 1) blocks = 1;
+    if (blocks > 1024) blocks = 1024;
+    hipLaunchKernelGGL(reset_kernel, dim3(blocks), dim3(256), 0, s, queue, stats, bad, npairs);
+    return hipGetLastError();
+}
+
+hipError_t launch_pack(const uint8_t* seq, const int64_t* off, const int64_t* wordoff, int32_t npairs,
+                       int64_t total_words, Plane2* out, uint8_t* bad, int num_cu, hipStream_t s) {
+    if (total_words <= 0 || npairs <= 0) return hipSuccess;
+    int64_t blocks = (total_words + 3) / 4;            // 4 waves per block
+    const int64_t cap = (int64_t)num_cu * 32;           // grid-stride beyond this
+    if (blocks > cap) blocks = cap;
+    hipLaunchKernelGGL(pack_kernel, dim3((unsigned)blocks), dim3(256), 0, s, seq, off, wordoff, npairs,
+                       total_words, out, bad);
+    return hipGetLastError();
+}

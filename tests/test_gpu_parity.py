@@ -1,0 +1,168 @@
+"""GPU path vs CPU oracle: bit-exact edits, text_end, status and full CIGAR
+operation streams, through the C ABI, on seeded synthetic workloads."""
+import numpy as np
+import pytest
+
+import oracle
+from paper_2208_09985_amd import synth
+from tests.gpu_helpers import compare, log
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    from paper_2208_09985_amd import api
+    return api.Context(0)
+
+
+def run_gpu(ctx, batch, **kw):
+    from paper_2208_09985_amd import api
+    return api.align_batch(ctx, batch, **kw)
+
+
+def check(ctx, batch, W=64, O=24, k=64, what="", **kw):
+    log(f"[parity] {what} pairs={batch.npairs} W={W} O={O} k={k} {kw}")
+    ref = oracle.align_batch(batch, W, O, k)
+    gpu = run_gpu(ctx, batch, W=W, O=O, k=k, **kw)
+    compare(batch, gpu, ref, what)
+    return gpu, ref
+
+
+def test_small_100bp_all_pairs_plain(ctx):
+    b = synth.make_batch("small_100bp")
+    gpu, ref = check(ctx, b, what="small_100bp plain")
+    assert gpu.stats.windows == ref["stats"].windows
+    assert gpu.stats.ops_alg == ref["stats"].ops_alg
+
+
+@pytest.mark.parametrize("mode,extra", [("fixed", dict(fixed_rows=1)), ("fixed", dict(fixed_rows=8)),
+                                        ("fixed", dict(fixed_rows=16)), ("plain", dict(slots=4)),
+                                        ("fixed", dict(fixed_rows=5, slots=16))])
+def test_small_100bp_budgets_and_packing(ctx, mode, extra):
+    b = synth.make_batch("small_100bp", 300)
+    gpu, ref = check(ctx, b, mode=mode, what=f"small_100bp {mode} {extra}", **extra)
+    if mode == "fixed" and extra["fixed_rows"] == 1:
+        assert gpu.stats.fallback_windows > 0
+
+
+def test_short_250bp_subset(ctx):
+    b = synth.make_batch("short_250bp", 20000)
+    check(ctx, b, what="short_250bp")
+    check(ctx, b, mode="fixed", fixed_rows=4, what="short_250bp fixed4")
+
+
+def test_long_10kbp_sample(ctx):
+    b = synth.make_batch("long_10kbp", 48)
+    check(ctx, b, what="long_10kbp")
+    check(ctx, b, mode="fixed", fixed_rows=16, what="long_10kbp fixed16")
+
+
+def test_uneven_and_mixed_samples(ctx):
+    check(ctx, synth.make_batch("uneven_lognormal", 64), order="longest_first", what="uneven_lognormal")
+    check(ctx, synth.make_batch("mixed_10kbp", 32), mode="fixed", fixed_rows=8, what="mixed_10kbp fixed8")
+
+
+@pytest.mark.parametrize("W,O,k", [(64, 33, 64), (32, 17, 32), (16, 9, 16), (8, 3, 8), (4, 3, 4), (64, 0, 64),
+                                   (64, 63, 64), (1, 0, 1), (48, 20, 30), (64, 24, 6)])
+def test_window_parameters(ctx, W, O, k):
+    rng = np.random.default_rng(W * 100 + O)
+    pats, txts = [], []
+    for _ in range(150):
+        p = synth.ALPHABET[rng.integers(0, 4, int(rng.integers(1, 400)))]
+        t = p.copy()
+        nedit = int(len(t) * rng.uniform(0, 0.3))
+        for _ in range(nedit):
+            pos = int(rng.integers(0, max(1, len(t))))
+            r = rng.random()
+            if r < 0.33 and len(t):
+                t[pos] = synth.ALPHABET[rng.integers(0, 4)]
+            elif r < 0.66:
+                t = np.insert(t, pos, synth.ALPHABET[rng.integers(0, 4)])
+            elif len(t):
+                t = np.delete(t, pos)
+        pats.append(p.tobytes())
+        txts.append(t.tobytes())
+    b = synth.from_lists(pats, txts)
+    check(ctx, b, W=W, O=O, k=k, what=f"W{W}O{O}k{k}")
+    check(ctx, b, W=W, O=O, k=k, mode="fixed", fixed_rows=3, what=f"W{W}O{O}k{k} fixed3")
+
+
+def test_edge_cases(ctx):
+    pats = [b"", b"ACGT", b"ACGTACGT", b"A", b"acgtNacgt".replace(b"N", b"a"), b"G" * 300, b"ACGT" * 40,
+            b"T" * 64, b"C" * 65, b"A" * 200]
+    txts = [b"ACGT", b"", b"ACGTACGT" + b"T" * 500, b"C", b"ACGTAACGT", b"G" * 10, b"", b"A" * 64, b"C" * 64,
+            b"T" * 200]
+    b = synth.from_lists(pats, txts)
+    check(ctx, b, what="edge cases")
+    check(ctx, b, k=5, what="edge cases k=5 (not aligned)")
+
+
+def test_bad_device_input_marks_pair(ctx):
+    from paper_2208_09985_amd import api
+    b = synth.from_lists([b"ACGT", b"ACNT", b"ACGT"], [b"ACGT", b"ACGT", b"AXGT"])
+    res = api.align_batch(ctx, b)
+    assert list(res.status) == [0, 2, 2]
+    assert list(res.edits) == [0, -1, -1]
+
+
+def test_host_input_rejects_bad_alphabet(ctx):
+    from paper_2208_09985_amd import api, _lib
+    b = synth.from_lists([b"ACNT"], [b"ACGT"])
+    with pytest.raises(_lib.ScgError) as e:
+        api.Batch(ctx, b, device_input=False)
+    assert e.value.code == _lib.EALPHABET
+
+
+def test_single_pair_api(ctx):
+    p, t = b"ACGTACGTTTGACCA" * 5, b"ACGTACGTTGACCAT" * 5
+    e, te, cg = ctx.align(p, t)
+    r = oracle.align_pair(p, t, 64, 24, 64)
+    assert (e, te, cg) == (r["edits"], r["text_end"], oracle.cigar(r["ops"]))
+
+
+def test_launch_shape_does_not_change_results(ctx):
+    b = synth.make_batch("long_10kbp", indices=range(100, 132))
+    ref = oracle.align_batch(b, 64, 24, 64)
+    for kw in (dict(slots=1, waves_per_cu=1), dict(slots=3, order="longest_first"), dict(slots=16, waves_per_cu=2)):
+        log(f"[parity] launch shape {kw}")
+        compare(b, run_gpu(ctx, b, mode="fixed", fixed_rows=12, **kw), ref, f"shape {kw}")
+
+
+def test_graph_replays_match_eager(ctx):
+    import torch
+    from paper_2208_09985_amd import api
+    b = synth.make_batch("short_250bp", 3000)
+    ref = oracle.align_batch(b, 64, 24, 64)
+    gb = api.Batch(ctx, b, api.params(graph=True, mode="fixed", fixed_rows=8))
+    for rep in range(4):
+        log(f"[parity] graph replay {rep}")
+        gb.edits.fill_(-7)
+        gb.run()
+        torch.cuda.synchronize()
+        compare(b, gb.result(), ref, f"graph replay {rep}")
+        _ = torch.ones(1000, device=gb.dev).sum().item()   # eager work between replays
+    gb.close()
+
+
+def test_long_10kbp_full_size_sampled(ctx):
+    """Full long-read workload (10,000 x 10 kbp) in the launch configuration the
+    benchmark times; the oracle recomputes a random sample of pairs."""
+    from paper_2208_09985_amd import api
+    b = synth.make_batch("long_10kbp")
+    log("[parity] long_10kbp full size on GPU")
+    gpu = api.align_batch(ctx, b)
+    idx = np.random.default_rng(99).choice(b.npairs, 40, replace=False)
+    sub = b.subset(idx)
+    ref = oracle.align_batch(sub, 64, 24, 64)
+    assert np.array_equal(np.asarray(gpu.edits)[idx], ref["edits"])
+    assert np.array_equal(np.asarray(gpu.text_end)[idx], ref["text_end"])
+    for j, i in enumerate(idx):
+        assert np.array_equal(gpu.ops(int(i)), oracle.ops_of(ref, j)), int(i)
+    assert np.all(np.asarray(gpu.status) == 0)
+    # every CIGAR consumes its whole pattern
+    lens = np.diff(b.pat_off)
+    ops_p = [int(np.sum(gpu.ops(int(i)) != 3)) for i in range(0, b.npairs, 97)]
+    assert ops_p == [int(lens[i]) for i in range(0, b.npairs, 97)]
