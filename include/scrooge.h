@@ -88,8 +88,11 @@ typedef struct {
 
 typedef struct {
     double kernel_ms;          /* alignment kernel time of the last run (HIP events)     */
-    double pack_ms;            /* encode/pack kernel time of the last run                */
-    int64_t windows;           /* windows aligned                                        */
+    double pack_ms;            /* encode/pack kernels of the last run                    */
+    double kernel_ms_avg;      /* mean alignment kernel time over the runs since the     */
+    double pack_ms_avg;        /*   previous scg_batch_stats call (at most 256 runs)     */
+    int64_t timed_runs;        /* number of runs in those means                          */
+    int64_t windows;           /* windows aligned (last run)                             */
     int64_t ops_alg;           /* sum over windows of (d_w+1) + 2 n_w + 7 n_w d_w        */
     int64_t fallback_windows;  /* windows recomputed after missing their budget          */
     int64_t lane_steps;        /* sum over passes of lanes x diagonal steps (work issued) */
@@ -156,7 +159,10 @@ int scg_batch_runs_offsets(const scg_batch* b, int64_t* out);
 int scg_batch_run(scg_batch* b, void* stream, int32_t* edits, int32_t* text_end, int32_t* status,
                   uint32_t* runs, int32_t* n_runs);
 
-/* Synchronise the batch's last run and read its counters and timings. */
+/* Synchronise the batch's last run and read its counters and timings.
+ * Timings come from HIP events recorded on the run's stream around the
+ * pack kernels and around the alignment kernel (graph replays: around the
+ * whole replay, reported as kernel time). */
 int scg_batch_stats(scg_batch* b, scg_stats* out);
 
 /* One pair in host memory (convenience; allocates and synchronises).

@@ -39,6 +39,7 @@ class Params(ctypes.Structure):
 class Stats(ctypes.Structure):
     _fields_ = [
         ("kernel_ms", ctypes.c_double), ("pack_ms", ctypes.c_double),
+        ("kernel_ms_avg", ctypes.c_double), ("pack_ms_avg", ctypes.c_double), ("timed_runs", ctypes.c_int64),
         ("windows", ctypes.c_int64), ("ops_alg", ctypes.c_int64), ("fallback_windows", ctypes.c_int64),
         ("lane_steps", ctypes.c_int64), ("rounds", ctypes.c_int64), ("rows_budgeted", ctypes.c_int64),
     ]

@@ -32,7 +32,7 @@ def _stream_ptr(stream) -> ctypes.c_void_p:
     return ctypes.c_void_p(stream.cuda_stream)
 
 
-def params(W=64, O=24, k=64, mode="plain", slots=0, waves_per_cu=0, order="input", fixed_rows=16, tau=0.9,
+def params(W=64, O=24, k=64, mode="plain", slots=0, waves_per_cu=0, order="input", fixed_rows=15, tau=0.9,
            graph=False) -> L.Params:
     p = L.Params()
     L.load().scg_params_default(ctypes.byref(p))

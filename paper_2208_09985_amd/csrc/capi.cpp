@@ -53,8 +53,11 @@ struct scg_batch {
     int ns = 1;
     int grid = 1;
     size_t lds = 0;
-    // timing
-    hipEvent_t ev[4] = {nullptr, nullptr, nullptr, nullptr};
+    // timing: a ring of (pack start, align start, align end) events, one per run
+    static constexpr int kRing = 256;
+    hipEvent_t ev[kRing][3] = {};
+    int ring_next = 0;      // slot of the next run
+    int ring_pending = 0;   // runs recorded since the last scg_batch_stats
     bool timed = false;
     // captured launch sequence
     hipGraph_t graph = nullptr;
@@ -108,8 +111,9 @@ void free_batch(scg_batch* b) {
     if (!b) return;
     if (b->gexec) (void)hipGraphExecDestroy(b->gexec);
     if (b->graph) (void)hipGraphDestroy(b->graph);
-    for (auto& e : b->ev)
-        if (e) (void)hipEventDestroy(e);
+    for (auto& trip : b->ev)
+        for (auto& e : trip)
+            if (e) (void)hipEventDestroy(e);
     void* ptrs[] = {b->own_seq ? b->pat_d : nullptr, b->own_seq ? b->txt_d : nullptr, b->pat_off_d, b->txt_off_d,
                     b->pplanes, b->tplanes, b->pword_d, b->tword_d, b->plen_d, b->tlen_d, b->bad_d, b->order_d,
                     b->runs_off_d, b->queue_d, b->stats_d};
@@ -121,11 +125,16 @@ void free_batch(scg_batch* b) {
 int enqueue_run(scg_batch* b, hipStream_t s, int32_t* edits, int32_t* text_end, int32_t* status, uint32_t* runs,
                 int32_t* n_runs, bool with_events) {
     const scg_ctx* c = b->ctx;
-    if (with_events) HIP_TRY(hipEventRecord(b->ev[0], s));
+    hipEvent_t* ev = b->ev[b->ring_next];
+    if (with_events) {
+        for (int i = 0; i < 3; ++i)
+            if (!ev[i]) HIP_TRY(hipEventCreate(&ev[i]));
+        HIP_TRY(hipEventRecord(ev[0], s));
+    }
     HIP_TRY(launch_reset(b->queue_d, b->stats_d, b->bad_d, b->npairs, s));
     HIP_TRY(launch_pack(b->pat_d, b->pat_off_d, b->pword_d, b->npairs, b->pwords, b->pplanes, b->bad_d, c->num_cu, s));
     HIP_TRY(launch_pack(b->txt_d, b->txt_off_d, b->tword_d, b->npairs, b->twords, b->tplanes, b->bad_d, c->num_cu, s));
-    if (with_events) HIP_TRY(hipEventRecord(b->ev[1], s));
+    if (with_events) HIP_TRY(hipEventRecord(ev[1], s));
     AlignArgs a{};
     a.pplanes = b->pplanes;
     a.tplanes = b->tplanes;
@@ -164,7 +173,11 @@ int enqueue_run(scg_batch* b, hipStream_t s, int32_t* edits, int32_t* text_end, 
     a.queue = b->queue_d;
     a.stats = b->stats_d;
     if (b->npairs > 0) HIP_TRY(launch_align(a, b->grid, b->lds, s));
-    if (with_events) HIP_TRY(hipEventRecord(b->ev[2], s));
+    if (with_events) {
+        HIP_TRY(hipEventRecord(ev[2], s));
+        b->ring_next = (b->ring_next + 1) % scg_batch::kRing;
+        b->ring_pending = std::min(b->ring_pending + 1, scg_batch::kRing);
+    }
     return SCG_OK;
 }
 
@@ -196,7 +209,7 @@ void scg_params_default(scg_params* p) {
     p->k = 64;
     p->mode = SCG_MODE_PLAIN;
     p->order = SCG_ORDER_INPUT;
-    p->fixed_rows = 16;
+    p->fixed_rows = 15;
     p->tau = 0.9f;
 }
 
@@ -351,13 +364,11 @@ int scg_batch_create(scg_ctx* c, const scg_params* params, int32_t npairs, const
     // launch shape
     b->ns = params->slots > 0 ? params->slots : (params->mode == SCG_MODE_PLAIN ? 1 : 8);
     b->lds = align_lds_bytes(params->W - params->O + 1, b->ns);
-    int per_cu = align_max_blocks_per_cu(b->lds);
+    int per_cu = align_max_blocks_per_cu(b->lds, params->mode == SCG_MODE_LEARNED);
     if (params->waves_per_cu > 0) per_cu = std::min(per_cu, params->waves_per_cu);
     b->grid = std::max(1, per_cu * c->num_cu);
     const int64_t need = (npairs + b->ns - 1) / b->ns;   // more wavefronts than slots-worth of pairs idle
     if (b->grid > need) b->grid = (int)std::max<int64_t>(1, need);
-    for (auto& e : b->ev)
-        if ((rc = from_hip(hipEventCreate(&e)))) return fail(rc);
     *out = b;
     return SCG_OK;
 }
@@ -410,9 +421,15 @@ int scg_batch_run(scg_batch* b, void* stream, int32_t* edits, int32_t* text_end,
         for (int i = 0; i < 6; ++i) b->gkey[i] = key[i];
     }
     b->timed = true;
-    HIP_TRY(hipEventRecord(b->ev[0], s));
+    hipEvent_t* ev = b->ev[b->ring_next];
+    for (int i = 0; i < 3; ++i)
+        if (!ev[i]) HIP_TRY(hipEventCreate(&ev[i]));
+    HIP_TRY(hipEventRecord(ev[0], s));
+    HIP_TRY(hipEventRecord(ev[1], s));
     HIP_TRY(hipGraphLaunch(b->gexec, s));
-    HIP_TRY(hipEventRecord(b->ev[2], s));
+    HIP_TRY(hipEventRecord(ev[2], s));
+    b->ring_next = (b->ring_next + 1) % scg_batch::kRing;
+    b->ring_pending = std::min(b->ring_pending + 1, scg_batch::kRing);
     return SCG_OK;
 }
 
@@ -421,19 +438,28 @@ int scg_batch_stats(scg_batch* b, scg_stats* out) {
     std::memset(out, 0, sizeof(*out));
     HIP_TRY(hipSetDevice(b->ctx->device));
     if (!b->timed) return SCG_OK;
-    HIP_TRY(hipEventSynchronize(b->ev[2]));
+    const int last = (b->ring_next + scg_batch::kRing - 1) % scg_batch::kRing;
+    HIP_TRY(hipEventSynchronize(b->ev[last][2]));
     unsigned long long st[ST_COUNT];
     HIP_TRY(hipMemcpy(st, b->stats_d, sizeof(st), hipMemcpyDeviceToHost));
-    float total = 0.f, pack = 0.f;
-    HIP_TRY(hipEventElapsedTime(&total, b->ev[0], b->ev[2]));
-    if (!(b->p.flags & SCG_FLAG_GRAPH)) {
-        HIP_TRY(hipEventElapsedTime(&pack, b->ev[0], b->ev[1]));
-        out->kernel_ms = total - pack;
-        out->pack_ms = pack;
-    } else {
-        out->kernel_ms = total;
-        out->pack_ms = 0.0;
+    // in graph mode the pack/align split is not observable: everything counts as kernel time
+    double ksum = 0.0, psum = 0.0;
+    for (int r = 0; r < b->ring_pending; ++r) {
+        hipEvent_t* ev = b->ev[(last + scg_batch::kRing - r) % scg_batch::kRing];
+        float pack = 0.f, kern = 0.f;
+        HIP_TRY(hipEventElapsedTime(&pack, ev[0], ev[1]));
+        HIP_TRY(hipEventElapsedTime(&kern, ev[1], ev[2]));
+        if (r == 0) {
+            out->kernel_ms = kern;
+            out->pack_ms = pack;
+        }
+        ksum += kern;
+        psum += pack;
     }
+    out->timed_runs = b->ring_pending;
+    out->kernel_ms_avg = b->ring_pending ? ksum / b->ring_pending : 0.0;
+    out->pack_ms_avg = b->ring_pending ? psum / b->ring_pending : 0.0;
+    b->ring_pending = 0;
     out->windows = (int64_t)st[ST_WINDOWS];
     out->ops_alg = (int64_t)st[ST_OPS_ALG];
     out->fallback_windows = (int64_t)st[ST_FALLBACK];

@@ -72,7 +72,7 @@ hipError_t launch_pack(const uint8_t* seq, const int64_t* off, const int64_t* wo
                        int64_t total_words, Plane2* out, uint8_t* bad, int num_cu, hipStream_t s);
 hipError_t launch_align(const AlignArgs& a, int grid, size_t lds_bytes, hipStream_t s);
 size_t align_lds_bytes(int ccols, int ns);
-int align_max_blocks_per_cu(size_t lds_bytes);
+int align_max_blocks_per_cu(size_t lds_bytes, bool learned);
 hipError_t launch_features(const Plane2* pplanes, const Plane2* tplanes, const int64_t* pword,
                            const int64_t* tword, const int32_t* plen, const int32_t* tlen, int32_t npairs,
                            int32_t W, int32_t nwin, const int32_t* windows, uint16_t* features, hipStream_t s);
