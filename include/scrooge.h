@@ -84,6 +84,8 @@ typedef struct {
     int32_t fixed_rows;     /* SCG_MODE_FIXED: rows computed before falling back       */
     float tau;              /* SCG_MODE_LEARNED: confidence needed for a smaller budget */
     int32_t flags;          /* SCG_FLAG_*                                              */
+    int32_t yield_chars;    /* a pair returns to the queue after advancing this many   */
+                            /* pattern characters (0 = never; else >= W-O)             */
 } scg_params;
 
 typedef struct {
@@ -98,6 +100,7 @@ typedef struct {
     int64_t lane_steps;        /* sum over passes of lanes x diagonal steps (work issued) */
     int64_t rounds;            /* wavefront rounds (one DC pass each)                    */
     int64_t rows_budgeted;     /* sum over window attempts of rows computed              */
+    int64_t yields;            /* times a pair went back to the queue                    */
 } scg_stats;
 
 typedef struct scg_ctx scg_ctx;
@@ -110,7 +113,8 @@ const char* scg_strerror(int code);
  * the call and the runtime's message.  Static per-thread storage. */
 const char* scg_last_hip_error(void);
 
-/* Default parameters: W=64, O=24, k=64, plain mode, automatic launch shape. */
+/* Default parameters: W=64, O=24, k=64, plain mode, automatic launch shape,
+ * yield_chars = 1280. */
 void scg_params_default(scg_params* p);
 
 /* Create a context on HIP device `device`.  *out receives the context; the

@@ -32,7 +32,7 @@ class Params(ctypes.Structure):
         ("W", ctypes.c_int32), ("O", ctypes.c_int32), ("k", ctypes.c_int32),
         ("mode", ctypes.c_int32), ("slots", ctypes.c_int32), ("waves_per_cu", ctypes.c_int32),
         ("order", ctypes.c_int32), ("fixed_rows", ctypes.c_int32), ("tau", ctypes.c_float),
-        ("flags", ctypes.c_int32),
+        ("flags", ctypes.c_int32), ("yield_chars", ctypes.c_int32),
     ]
 
 
@@ -42,6 +42,7 @@ class Stats(ctypes.Structure):
         ("kernel_ms_avg", ctypes.c_double), ("pack_ms_avg", ctypes.c_double), ("timed_runs", ctypes.c_int64),
         ("windows", ctypes.c_int64), ("ops_alg", ctypes.c_int64), ("fallback_windows", ctypes.c_int64),
         ("lane_steps", ctypes.c_int64), ("rounds", ctypes.c_int64), ("rows_budgeted", ctypes.c_int64),
+        ("yields", ctypes.c_int64),
     ]
 
 

@@ -33,7 +33,7 @@ def _stream_ptr(stream) -> ctypes.c_void_p:
 
 
 def params(W=64, O=24, k=64, mode="plain", slots=0, waves_per_cu=0, order="input", fixed_rows=15, tau=0.9,
-           graph=False) -> L.Params:
+           graph=False, yield_chars=None) -> L.Params:
     p = L.Params()
     L.load().scg_params_default(ctypes.byref(p))
     p.W, p.O, p.k = W, O, k
@@ -42,6 +42,8 @@ def params(W=64, O=24, k=64, mode="plain", slots=0, waves_per_cu=0, order="input
     p.order = {"input": L.ORDER_INPUT, "longest_first": L.ORDER_LONGEST_FIRST}[order]
     p.fixed_rows, p.tau = fixed_rows, tau
     p.flags = L.FLAG_GRAPH if graph else 0
+    if yield_chars is not None:
+        p.yield_chars = yield_chars
     return p
 
 

@@ -31,7 +31,10 @@
 //     runs are skipped with one XOR of the 2-bit planes and a trailing-zero
 //     count; only edit steps read LDS, and only row d-1.
 //   * Pairs are taken from a global atomic queue (the paper's global queue of
-//     pairs, Section 2.5) until it is empty; every wavefront then exits.
+//     pairs, Section 2.5).  A pair that has advanced yield_chars pattern
+//     characters saves its small state and goes back to the queue, so pairs
+//     whose windows need many rows do not pin one wavefront.  A wavefront
+//     exits when every pair is finished or none of its slots can receive one.
 //   * Row budgets: plain mode computes rows 0..k_w of every window.  The
 //     learned and fixed modes first compute fewer rows; a window that finds
 //     no d_w within them is retried with a larger budget (w -> 2w+1, at most
@@ -43,7 +46,7 @@ namespace {
 
 constexpr uint32_t kDppWaveShr1 = 0x138;
 constexpr int kEqPadBefore = 64;   // EQ-table entries before the first slot's table
-constexpr int kEqPadAfter = 192;   // and after the last one (reads of idle lanes land here)
+constexpr int kEqPadAfter = 72;    // and after the last one: reads reach index steps+6 <= 133 past a table start
 
 __device__ __forceinline__ uint32_t from_lower_lane(uint32_t x) {
     // lane l receives lane l-1's value; lane 0 receives 0
@@ -153,54 +156,81 @@ __global__ __launch_bounds__(64) void align_kernel(const AlignArgs a) {
     uint64_t* eqt = dent + (size_t)(a.ccols + 1) * 64;                         // pads + [NS][64]
     WinPlanes* wpl = (WinPlanes*)(eqt + kEqPadBefore + (size_t)NS * 64 + kEqPadAfter);  // [NS]
     SlotRec* srec = (SlotRec*)(wpl + NS);                                      // [NS]
+    PlaneBuf* pbufs = (PlaneBuf*)(srec + NS);                                  // [NS] pattern words
+    PlaneBuf* tbufs = pbufs + NS;                                              // [NS] text words
 
     const int cap = a.cap;
-    MlpRegs mlp;
-    if constexpr (LEARNED) mlp_load_regs(mlp, a.model.w1, a.model.b1, a.model.w2, a.model.b2, a.model.H, a.model.C, lane);
 
     // ---- slot-lane state (meaningful in lanes < NS) ----
     int pair = -1, p0 = 0, t0 = 0, m = 0, n = 0, edits = 0, nruns = 0, cur_op = 0, cur_len = 0;
-    int next_w = 0, bad_state = 0, pqmax = 0, tqmax = 0;
-    int64_t roff = 0, rcap = 0;
+    int next_w = 0, bad_state = 0, pqmax = 0, tqmax = 0, p0_take = 0;
+    int64_t roff = 0, rcap = 0, pending = -1;
+    int polled = 0;       // ring[pending] as last read (0: not yet written)
     const Plane2* pseq = nullptr;
     const Plane2* tseq = nullptr;
-    PlaneBuf pbuf{}, tbuf{};
     bool exhausted = lane >= NS;
-    unsigned long long c_windows = 0, c_ops = 0, c_fallback = 0, c_rows = 0, c_err = 0;
+    unsigned long long c_windows = 0, c_ops = 0, c_fallback = 0, c_rows = 0, c_err = 0, c_yield = 0;
     unsigned long long c_lane_steps = 0, c_rounds = 0;
     int rot = 0;
 
     for (;;) {
         // ---- 1. refill empty slots from the queue ----
-        if (!exhausted && pair < 0) {
-            for (;;) {
-                const uint32_t q = atomicAdd(a.queue, 1u);
-                if (q >= (uint32_t)a.npairs) { exhausted = true; break; }
-                const int pid = a.order[q];
-                const int pm = a.plen[pid], pn = a.tlen[pid];
-                if (a.bad[pid]) {
-                    a.edits[pid] = -1; a.text_end[pid] = -1; a.status[pid] = 2; a.n_runs[pid] = 0;
-                    continue;
-                }
-                if (pm == 0) {
-                    a.edits[pid] = 0; a.text_end[pid] = 0; a.status[pid] = 0; a.n_runs[pid] = 0;
-                    continue;
-                }
-                pair = pid; m = pm; n = pn; p0 = 0; t0 = 0; edits = 0; nruns = 0; cur_op = 0; cur_len = 0;
-                next_w = 0; bad_state = 0;
-                roff = a.runs_off[pid];
-                rcap = a.runs_off[pid + 1] - roff;
-                pseq = a.pplanes + a.pword[pid];
-                tseq = a.tplanes + a.tword[pid];
-                pqmax = (pm + 63) >> 6;   // the padding word
-                tqmax = (pn + 63) >> 6;
-                buf_fill(pbuf, pseq, 0, pqmax);
-                buf_fill(tbuf, tseq, 0, tqmax);
-                break;
+        // A slot reserves one queue index (pop) and keeps it until the entry
+        // is written: a yielding pair may reserve a tail index just before it
+        // stores there.  Pop and poll are issued during the previous round's
+        // DC pass and traceback, so a round waits on global memory only when
+        // a new pair starts (its saved state and first plane words).
+        auto activate = [&]() {
+            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+            const bool fresh = pending < a.npairs;
+            const int pid = polled - 1;
+            pending = -1;
+            polled = 0;
+            const int pm = a.plen[pid], pn = a.tlen[pid];
+            if (fresh && (a.bad[pid] || pm == 0)) {
+                const bool bad = a.bad[pid] != 0;
+                a.edits[pid] = bad ? -1 : 0;
+                a.text_end[pid] = bad ? -1 : 0;
+                a.status[pid] = bad ? 2 : 0;
+                a.n_runs[pid] = 0;
+                atomicAdd(&a.qctl[2], 1u);
+                return;
             }
+            pair = pid; m = pm; n = pn; bad_state = 0;
+            if (fresh) {
+                p0 = 0; t0 = 0; edits = 0; nruns = 0; cur_op = 0; cur_len = 0; next_w = 0;
+            } else {
+                const int32_t* st = a.pstate + 8 * (int64_t)pid;
+                p0 = st[0]; t0 = st[1]; edits = st[2]; nruns = st[3]; cur_op = st[4]; cur_len = st[5];
+                next_w = st[6];
+            }
+            p0_take = p0;
+            roff = a.runs_off[pid];
+            rcap = a.runs_off[pid + 1] - roff;
+            pseq = a.pplanes + a.pword[pid];
+            tseq = a.tplanes + a.tword[pid];
+            pqmax = (pm + 63) >> 6;   // the padding word
+            tqmax = (pn + 63) >> 6;
+            buf_fill(pbufs[lane], pseq, p0 >> 6, pqmax);
+            buf_fill(tbufs[lane], tseq, t0 >> 6, tqmax);
+        };
+        // with no active slot in the wavefront, pop and poll now
+        if (__ballot(pair >= 0 || (!exhausted && polled != 0)) == 0 && !exhausted && pair < 0) {
+            if (pending < 0) pending = (int64_t)atomicAdd(&a.qctl[0], 1u);
+            if (pending >= a.qcap) exhausted = true;
+            else polled = __hip_atomic_load(&a.ring[pending], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        }
+        if (!exhausted && pair < 0 && polled != 0) activate();
+        if (__ballot(pair >= 0) == 0) {
+            // leave once every pair is finished or no slot can ever receive
+            // one; otherwise wait for yielded pairs
+            const bool waiting = !exhausted && pair < 0;
+            if (__ballot(waiting) == 0) break;
+            if (__hip_atomic_load(&a.qctl[2], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) >= (uint32_t)a.npairs) break;
+            __builtin_amdgcn_s_sleep(16);
+            continue;
         }
         const bool active = pair >= 0;
-        if (__ballot(active) == 0) break;
 
         // ---- 2. window geometry of each active slot ----
         int mw = 0, nw = 0, kw = 0, rows_full = 0, w = 0;
@@ -210,11 +240,15 @@ __global__ __launch_bounds__(64) void align_kernel(const AlignArgs a) {
             nw = min(a.W, n - t0);
             kw = min(a.k, mw);
             rows_full = (kw == mw) ? mw : kw + 1;   // row m_w is implicit: D(0,0) <= m_w
-            buf_seek(pbuf, pseq, p0 >> 6, pqmax);
-            buf_window(pbuf, p0, wp.plo, wp.phi);
+            PlaneBuf pb = pbufs[lane];
+            buf_seek(pb, pseq, p0 >> 6, pqmax);
+            buf_window(pb, p0, wp.plo, wp.phi);
+            pbufs[lane] = pb;
             if (nw > 0) {
-                buf_seek(tbuf, tseq, t0 >> 6, tqmax);
-                buf_window(tbuf, t0, wp.tlo, wp.thi);
+                PlaneBuf tb = tbufs[lane];
+                buf_seek(tb, tseq, t0 >> 6, tqmax);
+                buf_window(tb, t0, wp.tlo, wp.thi);
+                tbufs[lane] = tb;
             }
             wp.m_w = mw;
             wp.n_w = nw;
@@ -226,6 +260,10 @@ __global__ __launch_bounds__(64) void align_kernel(const AlignArgs a) {
 
         // ---- 3. learned row budget: features -> MLP (MFMA) -> smallest confident budget ----
         if constexpr (LEARNED) {
+            // operand registers are reloaded each round (L1-resident weights)
+            // so they do not stay live across the DC pass
+            MlpRegs mlp;
+            mlp_load_packed(mlp, a.model.operands, lane);
             __syncthreads();
             const int s = lane & 15, g = lane >> 4;
             half4_t x4 = {0, 0, 0, 0};
@@ -254,13 +292,20 @@ __global__ __launch_bounds__(64) void align_kernel(const AlignArgs a) {
         if (active) w = max(w, 1);
 
         // ---- 4. pack scheduled windows into lane segments (one gap lane after each) ----
+        // Widest first (threshold passes), rotating within a pass: a window
+        // that needs many rows is never starved by narrow ones filling the
+        // wavefront, and narrow windows fill what is left.
         int mybase = -1, used = 0;
-        for (int t = 0; t < NS; ++t) {
-            const int s = (rot + t) % NS;
-            const int ws = __builtin_amdgcn_readlane(w, s);
-            if (ws > 0 && used + ws <= 64) {
-                if (lane == s) mybase = used;
-                used += ws + 1;
+        for (int pass = 0; pass < 4; ++pass) {
+            const int lo = pass == 0 ? 33 : (pass == 1 ? 17 : (pass == 2 ? 9 : 1));
+            const int hi = pass == 0 ? 65 : (pass == 1 ? 33 : (pass == 2 ? 17 : 9));
+            for (int t = 0; t < NS; ++t) {
+                const int s = (rot + t) % NS;
+                const int ws = __builtin_amdgcn_readlane(w, s);
+                if (ws >= lo && ws < hi && used + ws <= 64) {
+                    if (lane == s) mybase = used;
+                    used += ws + 1;
+                }
             }
         }
         rot = (rot + 1) % NS;
@@ -293,6 +338,10 @@ __global__ __launch_bounds__(64) void align_kernel(const AlignArgs a) {
             }
         }
         __syncthreads();
+
+        // empty slots reserve their next queue index now; the atomic's
+        // latency hides behind the DC pass
+        if (!exhausted && pair < 0 && pending < 0) pending = (int64_t)atomicAdd(&a.qctl[0], 1u);
 
         // ---- 6. DC pass over the anti-diagonals ----
         if (!inseg) rnw = 0;
@@ -328,6 +377,12 @@ __global__ __launch_bounds__(64) void align_kernel(const AlignArgs a) {
         c_lane_steps += (unsigned long long)min(used, 64) * s;
         c_rounds += 1;
         __syncthreads();
+
+        // poll reserved queue entries; read at the next round's start
+        if (!exhausted && pair < 0 && pending >= 0 && polled == 0) {
+            if (pending >= a.qcap) exhausted = true;
+            else polled = __hip_atomic_load(&a.ring[pending], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        }
 
         // ---- 7. decide d_w, trace back, advance (slot lanes) ----
         if (active && mybase >= 0) {
@@ -393,6 +448,19 @@ __global__ __launch_bounds__(64) void align_kernel(const AlignArgs a) {
                     a.status[pair] = ok ? 0 : 3;
                     a.n_runs[pair] = ok ? nruns : 0;
                     pair = -1;
+                    atomicAdd(&a.qctl[2], 1u);
+                } else if (a.yield_chars > 0 && p0 - p0_take >= a.yield_chars) {
+                    // hand the pair back to the queue so that the pairs of a
+                    // wavefront rotate and the wavefronts stay balanced
+                    const uint32_t t = atomicAdd(&a.qctl[1], 1u);
+                    if ((int64_t)t < a.qcap) {
+                        int32_t* st = a.pstate + 8 * (int64_t)pair;
+                        st[0] = p0; st[1] = t0; st[2] = edits; st[3] = nruns; st[4] = cur_op; st[5] = cur_len;
+                        st[6] = next_w; st[7] = 0;
+                        __hip_atomic_store(&a.ring[t], pair + 1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+                        pair = -1;
+                        c_yield += 1;
+                    }
                 }
             } else if (not_aligned) {
                 c_windows += 1;
@@ -402,6 +470,7 @@ __global__ __launch_bounds__(64) void align_kernel(const AlignArgs a) {
                 a.status[pair] = 1;
                 a.n_runs[pair] = 0;
                 pair = -1;
+                atomicAdd(&a.qctl[2], 1u);
             }
         }
         __syncthreads();
@@ -414,6 +483,7 @@ __global__ __launch_bounds__(64) void align_kernel(const AlignArgs a) {
         if (c_fallback) atomicAdd(&a.stats[ST_FALLBACK], c_fallback);
         if (c_rows) atomicAdd(&a.stats[ST_ROWS], c_rows);
         if (c_err) atomicAdd(&a.stats[ST_ERRORS], c_err);
+        if (c_yield) atomicAdd(&a.stats[ST_YIELDS], c_yield);
     }
     if (lane == 0) {
         atomicAdd(&a.stats[ST_LANE_STEPS], c_lane_steps);
@@ -427,7 +497,7 @@ __global__ __launch_bounds__(64) void align_kernel(const AlignArgs a) {
 
 size_t align_lds_bytes(int ccols, int ns) {
     return (size_t)(ccols + 1) * 64 * 8 + (size_t)(kEqPadBefore + ns * 64 + kEqPadAfter) * 8 +
-           (size_t)ns * sizeof(WinPlanes) + (size_t)ns * sizeof(SlotRec);
+           (size_t)ns * sizeof(WinPlanes) + (size_t)ns * sizeof(SlotRec) + 2 * (size_t)ns * sizeof(PlaneBuf);
 }
 
 int align_max_blocks_per_cu(size_t lds_bytes, bool learned) {

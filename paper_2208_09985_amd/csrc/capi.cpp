@@ -7,6 +7,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <cmath>
 #include <cstdio>
 #include <cstring>
 #include <new>
@@ -23,6 +24,7 @@ struct scg_ctx {
     int F = 0, H = 0, C = 0;
     __half* model_d = nullptr;      // w1 | b1 | w2 | b2
     int32_t* budget_d = nullptr;
+    uint32_t* operands_d = nullptr; // per-lane MFMA operand blob (64 lanes x 144 B)
 };
 
 struct scg_batch {
@@ -47,7 +49,10 @@ struct scg_batch {
     int32_t* order_d = nullptr;
     int64_t* runs_off_d = nullptr;
     std::vector<int64_t> runs_off_h;
-    uint32_t* queue_d = nullptr;
+    uint32_t* qctl_d = nullptr;
+    int32_t* ring_d = nullptr;
+    int64_t qcap = 0;
+    int32_t* pstate_d = nullptr;
     unsigned long long* stats_d = nullptr;
     // launch shape
     int ns = 1;
@@ -104,6 +109,7 @@ int check_params(const scg_params* p) {
     if (p->order != SCG_ORDER_INPUT && p->order != SCG_ORDER_LONGEST_FIRST) return SCG_EINVAL;
     if (p->mode == SCG_MODE_FIXED && (p->fixed_rows < 1 || p->fixed_rows > 64)) return SCG_EINVAL;
     if (p->mode == SCG_MODE_LEARNED && !(p->tau > 0.f && p->tau <= 1.f)) return SCG_EINVAL;
+    if (p->yield_chars != 0 && p->yield_chars < p->W - p->O) return SCG_EINVAL;
     return SCG_OK;
 }
 
@@ -116,7 +122,7 @@ void free_batch(scg_batch* b) {
             if (e) (void)hipEventDestroy(e);
     void* ptrs[] = {b->own_seq ? b->pat_d : nullptr, b->own_seq ? b->txt_d : nullptr, b->pat_off_d, b->txt_off_d,
                     b->pplanes, b->tplanes, b->pword_d, b->tword_d, b->plen_d, b->tlen_d, b->bad_d, b->order_d,
-                    b->runs_off_d, b->queue_d, b->stats_d};
+                    b->runs_off_d, b->qctl_d, b->ring_d, b->pstate_d, b->stats_d};
     for (void* q : ptrs)
         if (q) (void)hipFree(q);
     delete b;
@@ -131,7 +137,7 @@ int enqueue_run(scg_batch* b, hipStream_t s, int32_t* edits, int32_t* text_end, 
             if (!ev[i]) HIP_TRY(hipEventCreate(&ev[i]));
         HIP_TRY(hipEventRecord(ev[0], s));
     }
-    HIP_TRY(launch_reset(b->queue_d, b->stats_d, b->bad_d, b->npairs, s));
+    HIP_TRY(launch_reset(b->qctl_d, b->ring_d, b->qcap, b->order_d, b->stats_d, b->bad_d, b->npairs, s));
     HIP_TRY(launch_pack(b->pat_d, b->pat_off_d, b->pword_d, b->npairs, b->pwords, b->pplanes, b->bad_d, c->num_cu, s));
     HIP_TRY(launch_pack(b->txt_d, b->txt_off_d, b->tword_d, b->npairs, b->twords, b->tplanes, b->bad_d, c->num_cu, s));
     if (with_events) HIP_TRY(hipEventRecord(ev[1], s));
@@ -155,6 +161,7 @@ int enqueue_run(scg_batch* b, hipStream_t s, int32_t* edits, int32_t* text_end, 
     a.ccols = a.cap + 1;
     if (b->p.mode == SCG_MODE_LEARNED) {
         const int F = c->F, H = c->H, C = c->C;
+        a.model.operands = reinterpret_cast<const uint4*>(c->operands_d);
         a.model.w1 = c->model_d;
         a.model.b1 = c->model_d + F * H;
         a.model.w2 = c->model_d + F * H + H;
@@ -170,7 +177,11 @@ int enqueue_run(scg_batch* b, hipStream_t s, int32_t* edits, int32_t* text_end, 
     a.runs = runs;
     a.runs_off = b->runs_off_d;
     a.n_runs = n_runs;
-    a.queue = b->queue_d;
+    a.ring = b->ring_d;
+    a.qcap = b->qcap;
+    a.qctl = b->qctl_d;
+    a.pstate = b->pstate_d;
+    a.yield_chars = b->p.yield_chars;
     a.stats = b->stats_d;
     if (b->npairs > 0) HIP_TRY(launch_align(a, b->grid, b->lds, s));
     if (with_events) {
@@ -211,6 +222,7 @@ void scg_params_default(scg_params* p) {
     p->order = SCG_ORDER_INPUT;
     p->fixed_rows = 15;
     p->tau = 0.9f;
+    p->yield_chars = 1280;
 }
 
 int scg_create(scg_ctx** out, int device) {
@@ -234,6 +246,7 @@ void scg_destroy(scg_ctx* c) {
     if (!c) return;
     if (c->model_d) (void)hipFree(c->model_d);
     if (c->budget_d) (void)hipFree(c->budget_d);
+    if (c->operands_d) (void)hipFree(c->operands_d);
     delete c;
 }
 
@@ -257,15 +270,48 @@ int scg_set_model(scg_ctx* c, int32_t F, int32_t H, int32_t C, const uint16_t* w
     std::memcpy(blob.data() + F * H + H + H * C, b2, sizeof(uint16_t) * C);
     if (c->model_d) (void)hipFree(c->model_d);
     if (c->budget_d) (void)hipFree(c->budget_d);
+    if (c->operands_d) (void)hipFree(c->operands_d);
     c->model_d = nullptr;
     c->budget_d = nullptr;
+    c->operands_d = nullptr;
     c->has_model = false;
+    // MFMA operand registers per lane (layout of mlp_load_packed): lane l
+    // holds column l%16 and k-group l/16 of each 16x16x16 operand
+    std::vector<uint32_t> op(64 * 36, 0);
+    auto h2f = [](uint16_t x) {
+        const uint32_t s = (x >> 15) & 1, e = (x >> 10) & 31, m = x & 1023;
+        float v;
+        if (e == 0) v = std::ldexp((float)m, -24);
+        else if (e == 31) v = m ? NAN : INFINITY;
+        else v = std::ldexp((float)(m | 1024), (int)e - 25);
+        return s ? -v : v;
+    };
+    auto put_f = [&](int word, float v) { std::memcpy(&op[word], &v, 4); };
+    auto put_h = [&](int lane, int idx, uint16_t v) {   // idx-th half of the lane's first 16 words
+        uint32_t& w = op[lane * 36 + idx / 2];
+        w = (idx & 1) ? ((w & 0xffffu) | ((uint32_t)v << 16)) : ((w & 0xffff0000u) | v);
+    };
+    for (int l = 0; l < 64; ++l) {
+        const int col = l & 15, grp = l >> 4;
+        const int fw = l * 36 + 16;
+        for (int b = 0; b < 4; ++b)
+            for (int e = 0; e < 4; ++e) {
+                const int f = 4 * grp + e, h = 16 * b + col, hk = 16 * b + 4 * grp + e;
+                put_h(l, b * 4 + e, h < H ? w1[f * H + h] : 0);                          // w1a
+                put_h(l, 16 + b * 4 + e, (hk < H && col < C) ? w2[hk * C + col] : 0);    // w2a
+                put_f(fw + b * 4 + e, hk < H ? h2f(b1[hk]) : 0.f);                      // b1c
+            }
+        for (int e = 0; e < 4; ++e) put_f(fw + 16 + e, (4 * grp + e) < C ? h2f(b2[4 * grp + e]) : 0.f);  // b2c
+    }
     int rc = dev_alloc(&c->model_d, n);
     if (rc) return rc;
     rc = dev_alloc(&c->budget_d, (size_t)C);
     if (rc) return rc;
     HIP_TRY(hipMemcpy(c->model_d, blob.data(), n * sizeof(uint16_t), hipMemcpyHostToDevice));
     HIP_TRY(hipMemcpy(c->budget_d, budget_rows, C * sizeof(int32_t), hipMemcpyHostToDevice));
+    rc = dev_alloc(&c->operands_d, op.size());
+    if (rc) return rc;
+    HIP_TRY(hipMemcpy(c->operands_d, op.data(), op.size() * sizeof(uint32_t), hipMemcpyHostToDevice));
     c->F = F;
     c->H = H;
     c->C = C;
@@ -318,6 +364,11 @@ int scg_batch_create(scg_ctx* c, const scg_params* params, int32_t npairs, const
     }
     b->pwords = pw[npairs];
     b->twords = tw[npairs];
+    // queue capacity: the initial order plus one entry per yield; a pair
+    // yields only after advancing yield_chars pattern characters
+    b->qcap = npairs;
+    if (params->yield_chars > 0)
+        for (int32_t i = 0; i < npairs; ++i) b->qcap += pl[i] / params->yield_chars + 1;
     std::vector<int32_t> order(npairs);
     std::iota(order.begin(), order.end(), 0);
     if (params->order == SCG_ORDER_LONGEST_FIRST)
@@ -333,7 +384,8 @@ int scg_batch_create(scg_ctx* c, const scg_params* params, int32_t npairs, const
         (rc = dev_alloc(&b->pword_d, npairs + 1)) || (rc = dev_alloc(&b->tword_d, npairs + 1)) ||
         (rc = dev_alloc(&b->plen_d, npairs)) || (rc = dev_alloc(&b->tlen_d, npairs)) ||
         (rc = dev_alloc(&b->bad_d, npairs)) || (rc = dev_alloc(&b->order_d, npairs)) ||
-        (rc = dev_alloc(&b->runs_off_d, npairs + 1)) || (rc = dev_alloc(&b->queue_d, 1)) ||
+        (rc = dev_alloc(&b->runs_off_d, npairs + 1)) || (rc = dev_alloc(&b->qctl_d, 4)) ||
+        (rc = dev_alloc(&b->ring_d, (size_t)b->qcap)) || (rc = dev_alloc(&b->pstate_d, (size_t)npairs * 8)) ||
         (rc = dev_alloc(&b->stats_d, ST_COUNT)))
         return fail(rc);
     if (where == SCG_WHERE_HOST) {
@@ -466,6 +518,7 @@ int scg_batch_stats(scg_batch* b, scg_stats* out) {
     out->lane_steps = (int64_t)st[ST_LANE_STEPS];
     out->rounds = (int64_t)st[ST_ROUNDS];
     out->rows_budgeted = (int64_t)st[ST_ROWS];
+    out->yields = (int64_t)st[ST_YIELDS];
     if (st[ST_ERRORS]) return SCG_EINTERNAL;
     return SCG_OK;
 }
@@ -529,7 +582,7 @@ int scg_features(scg_batch* b, int32_t nwin, const int32_t* windows, uint16_t* f
     HIP_TRY(hipSetDevice(b->ctx->device));
     hipStream_t s = (hipStream_t)stream;
     // planes are produced by the pack step of a run; make sure they exist
-    HIP_TRY(launch_reset(b->queue_d, b->stats_d, b->bad_d, b->npairs, s));
+    HIP_TRY(launch_reset(b->qctl_d, b->ring_d, b->qcap, b->order_d, b->stats_d, b->bad_d, b->npairs, s));
     HIP_TRY(launch_pack(b->pat_d, b->pat_off_d, b->pword_d, b->npairs, b->pwords, b->pplanes, b->bad_d,
                         b->ctx->num_cu, s));
     HIP_TRY(launch_pack(b->txt_d, b->txt_off_d, b->tword_d, b->npairs, b->twords, b->tplanes, b->bad_d,

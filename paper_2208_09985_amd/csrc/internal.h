@@ -22,6 +22,7 @@ enum {
     ST_ROUNDS,
     ST_ROWS,
     ST_ERRORS,
+    ST_YIELDS,
     ST_COUNT = 8
 };
 
@@ -31,6 +32,7 @@ constexpr int kMaxHidden = 64;
 constexpr int kFeatures = 16;
 
 struct ModelDev {
+    const uint4* operands;  // per-lane MFMA operand registers (mlp_load_packed)
     const __half* w1;   // [F][H]
     const __half* b1;   // [H]
     const __half* w2;   // [H][C]
@@ -61,13 +63,20 @@ struct AlignArgs {
     uint32_t* runs;
     const int64_t* runs_off;
     int32_t* n_runs;
-    uint32_t* queue;              // [0]: next queue position
+    // Pair queue: ring[q] = pair + 1 once written (0 = reserved, not yet
+    // written).  Entries [0, npairs) hold the initial order; a pair that
+    // yields is appended at qctl[1] with its state saved in pstate.
+    int32_t* ring;
+    int64_t qcap;
+    uint32_t* qctl;               // [0] head, [1] tail, [2] pairs finished
+    int32_t* pstate;              // per pair: p0, t0, edits, nruns, cur_op, cur_len, next_w, 0
+    int32_t yield_chars;          // a pair yields after advancing this many pattern chars (<= 0: never)
     unsigned long long* stats;    // ST_COUNT counters
 };
 
 // launchers (defined in the .hip files)
-hipError_t launch_reset(uint32_t* queue, unsigned long long* stats, uint8_t* bad, int32_t npairs,
-                        hipStream_t s);
+hipError_t launch_reset(uint32_t* qctl, int32_t* ring, int64_t qcap, const int32_t* order,
+                        unsigned long long* stats, uint8_t* bad, int32_t npairs, hipStream_t s);
 hipError_t launch_pack(const uint8_t* seq, const int64_t* off, const int64_t* wordoff, int32_t npairs,
                        int64_t total_words, Plane2* out, uint8_t* bad, int num_cu, hipStream_t s);
 hipError_t launch_align(const AlignArgs& a, int grid, size_t lds_bytes, hipStream_t s);

@@ -10,12 +10,19 @@
 
 namespace {
 
-__global__ __launch_bounds__(256) void reset_kernel(uint32_t* queue, unsigned long long* stats, uint8_t* bad,
+__global__ __launch_bounds__(256) void reset_kernel(uint32_t* qctl, int32_t* ring, int64_t qcap,
+                                                    const int32_t* order, unsigned long long* stats, uint8_t* bad,
                                                     int32_t npairs) {
     const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (t == 0) queue[0] = 0;
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    if (t == 0) {
+        qctl[0] = 0;                 // head
+        qctl[1] = (uint32_t)npairs;  // tail: the initial order is already queued
+        qctl[2] = 0;                 // pairs finished
+    }
     if (t < ST_COUNT) stats[t] = 0;
-    for (int64_t x = t; x < npairs; x += (int64_t)gridDim.x * blockDim.x) bad[x] = 0;
+    for (int64_t x = t; x < npairs; x += stride) bad[x] = 0;
+    for (int64_t x = t; x < qcap; x += stride) ring[x] = x < npairs ? order[x] + 1 : 0;
 }
 
 __device__ __forceinline__ int base_code(uint32_t c, bool& bad) {
@@ -62,11 +69,13 @@ __global__ __launch_bounds__(256) void pack_kernel(const uint8_t* __restrict__ s
 
 }  // namespace
 
-hipError_t launch_reset(uint32_t* queue, unsigned long long* stats, uint8_t* bad, int32_t npairs, hipStream_t s) {
-    int blocks = (int)((npairs + 255) / 256);
+hipError_t launch_reset(uint32_t* qctl, int32_t* ring, int64_t qcap, const int32_t* order,
+                        unsigned long long* stats, uint8_t* bad, int32_t npairs, hipStream_t s) {
+    int64_t blocks = (qcap + 255) / 256;
     if (blocks < 1) blocks = 1;
-    if (blocks > 1024) blocks = 1024;
-    hipLaunchKernelGGL(reset_kernel, dim3(blocks), dim3(256), 0, s, queue, stats, bad, npairs);
+    if (blocks > 2048) blocks = 2048;
+    hipLaunchKernelGGL(reset_kernel, dim3((unsigned)blocks), dim3(256), 0, s, qctl, ring, qcap, order, stats, bad,
+                       npairs);
     return hipGetLastError();
 }
 

@@ -97,6 +97,20 @@ __device__ inline void mlp_load_regs(MlpRegs& r, const __half* w1, const __half*
     }
 }
 
+// The same registers from a host-prepared blob: per lane 9 x 16 bytes in the
+// order w1a[0..3] (32 B), w2a[0..3] (32 B), b1c[0..3] (64 B), b2c (16 B).
+constexpr int kMlpOperandWords = 9;   // uint4 per lane
+
+__device__ __forceinline__ void mlp_load_packed(MlpRegs& r, const uint4* __restrict__ blob, int lane) {
+    const uint4* q = blob + kMlpOperandWords * lane;
+    uint4 v[kMlpOperandWords];
+    for (int i = 0; i < kMlpOperandWords; ++i) v[i] = q[i];
+    __builtin_memcpy(&r.w1a[0], &v[0], 32);
+    __builtin_memcpy(&r.w2a[0], &v[2], 32);
+    __builtin_memcpy(&r.b1c[0], &v[4], 64);
+    __builtin_memcpy(&r.b2c, &v[8], 16);
+}
+
 // x4: features 4*(lane/16)..+3 of sample lane%16, already scaled, as fp16.
 // Returns logits: lane l holds classes 4*(l/16)+e of sample l%16.
 // hid[b] receives relu(hidden) 16b + 4*(l/16) + e of sample l%16 (fp16).

@@ -166,3 +166,20 @@ def test_long_10kbp_full_size_sampled(ctx):
     lens = np.diff(b.pat_off)
     ops_p = [int(np.sum(gpu.ops(int(i)) != 3)) for i in range(0, b.npairs, 97)]
     assert ops_p == [int(lens[i]) for i in range(0, b.npairs, 97)]
+
+
+@pytest.mark.parametrize("yield_chars,kw", [(40, dict(mode="fixed", fixed_rows=7, slots=4)), (40, dict()),
+                                            (0, dict(mode="fixed", fixed_rows=15, slots=6)),
+                                            (100, dict(mode="fixed", fixed_rows=11, slots=16, waves_per_cu=1))])
+def test_yielding_queue_keeps_results(ctx, yield_chars, kw):
+    """Pairs handed back to the queue every few windows (state saved and
+    resumed on another wavefront) give the same alignments."""
+    b = synth.make_batch("uneven_lognormal", indices=range(200, 260))
+    ref = oracle.align_batch(b, 64, 24, 64)
+    log(f"[parity] yield_chars={yield_chars} {kw}")
+    gpu = run_gpu(ctx, b, yield_chars=yield_chars, **kw)
+    compare(b, gpu, ref, f"yield {yield_chars} {kw}")
+    if yield_chars:
+        assert gpu.stats.yields > 0
+    else:
+        assert gpu.stats.yields == 0
