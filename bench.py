@@ -10,18 +10,27 @@ Prints ONE JSON line on stdout; progress goes to stderr.
 Headline: plain row budget (every window may use all rows 0..k_w) on
 10,000 pairs of 10 kbp with 15% edits, W=64, O=24, k=64.  Variants on the
 same input: a constant row budget and the learned row budget, both with
-full-row fallback (all bit-identical to plain; checked here).
+full-row fallback (all bit-identical to plain; checked here).  Two more
+workloads are reported under "workloads": 10,000 x 10 kbp pairs with a
+per-pair edit rate of 5-15% (learned vs plain), and 50,000 pairs of
+log-normal length (1-50 kbp) as one hipGraph-captured launch with the launch
+shape picked by the autotuner.
 
 Roofline: the kernel is bound by 32-bit bitwise VALU issue.  One 64-bit op of
 the paper's accounting is two 32-bit lane operations, so the peak is
 256 CU x 64 lanes x 2.4 GHz / 2 = 19.66 T 64-bit op/s.  `achieved` is
 ops_alg (sum over windows of (d_w+1) + 2 n_w + 7 n_w d_w) per launch divided
 by the kernel's mean duration from HIP events recorded around each timed
-launch on its stream.
+launch on its stream.  `traffic` (HBM bytes per launch) comes from the
+committed rocprofv3 counter summary when it was taken from the current kernel
+sources (their hash is recorded beside the figures), else it is null.
+
+    python bench.py --copy-probe 1024   # device copy of 1 GiB, for counter calibration
 """
 from __future__ import annotations
 
 import argparse
+import hashlib
 import json
 import os
 import sys
@@ -35,6 +44,8 @@ sys.path.insert(0, ROOT)
 PEAK_T64OPS = 256 * 64 * 2.4e9 / 2 / 1e12     # 19.66 T 64-bit op/s
 METRIC = "alignments/s and Gbitops/s vs roofline, 10 kbp @15% err; learned-k vs plain"
 WEIGHTS = os.path.join(ROOT, "paper_2208_09985_amd", "weights", "budget_w64_o24.npz")
+TRAFFIC = os.path.join(ROOT, "profiles", "align_kernel_long_10kbp_traffic.txt")
+KERNEL_SOURCES = ("align.hip", "predictor.h", "internal.h")
 
 
 def log(*a):
@@ -89,6 +100,49 @@ def cpu_baseline(workload, W, O, k, budget_core_s=15.0):
             "ops_alg_per_s": round(res["stats"].ops_alg / dt, 1)}
 
 
+def spec(t):
+    """("fixed", x) -> x; other distributions -> "kind(a, b, ...)"."""
+    return t[1] if t[0] == "fixed" else f"{t[0]}{tuple(t[1:])}"
+
+
+def kernel_source_hash() -> str:
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, "paper_2208_09985_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic(kernel: str):
+    """HBM bytes per launch of `kernel` from the committed counter summary,
+    or None when the summary is missing or was taken from other sources."""
+    if not os.path.exists(TRAFFIC):
+        return None
+    vals = {}
+    for line in open(TRAFFIC):
+        if ":" in line and not line.startswith("#"):
+            k, v = line.split(":", 1)
+            vals[k.strip()] = v.strip()
+    if vals.get("source_hash") != kernel_source_hash():
+        return None
+    try:
+        return int(float(vals[f"{kernel}.hbm_bytes_per_launch"]))
+    except (KeyError, ValueError):
+        return None
+
+
+def copy_probe(mib: int, reps: int = 5):
+    """A plain device copy of known size (counter calibration)."""
+    import torch
+    n = mib * (1 << 20) // 4
+    src = torch.ones(n, dtype=torch.float32, device="cuda")
+    dst = torch.empty_like(src)
+    for _ in range(reps):
+        dst.copy_(src)
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_probe_bytes_each_way": n * 4, "reps": reps}), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -97,27 +151,30 @@ def main():
     ap.add_argument("--workload", default="long_10kbp")
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle CPU baseline")
     ap.add_argument("--no-variants", action="store_true", help="only the plain headline")
+    ap.add_argument("--no-workloads", action="store_true", help="skip the extra workloads")
     ap.add_argument("--fixed-rows", type=int, default=15)
+    ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
-        print("bench.py measures one GPU only: every pair is independent and this build runs on a "
-              "single MI355X; run with --gpus 1.", file=sys.stderr)
+        print("bench.py measures one GPU only: pairs are independent, so several GPUs would each run this "
+              "kernel on their own share of the pairs; run with --gpus 1.", file=sys.stderr)
         sys.exit(2)
+    if args.copy_probe:
+        copy_probe(args.copy_probe)
+        return
 
     import torch
-    from paper_2208_09985_amd import api, synth
-
-    w = synth.WORKLOADS[args.workload]
-    log(f"[bench] generating {args.workload} ({w.npairs} pairs)")
-    t = time.perf_counter()
-    batch = synth.make_batch(args.workload)
-    log(f"[bench] generated in {time.perf_counter() - t:.1f}s: {batch.pat.size} + {batch.txt.size} bases")
+    from paper_2208_09985_amd import api, autotune, synth
 
     ctx = api.Context(0)
-    def measure(name, prm):
+    have_model = os.path.exists(WEIGHTS)
+    if have_model:
+        ctx.load_model(WEIGHTS)
+
+    def measure(batch, name, prm, steps, warmup):
         log(f"[bench] {name}: prepare")
         b = api.Batch(ctx, batch, prm)
-        ms, st = timed_steps(b, args.steps, args.warmup)
+        ms, st = timed_steps(b, steps, warmup)
         res = b.result()
         ok = bool(np.all(res.status == 0))
         log(f"[bench] {name}: {ms:.3f} ms/step, kernel {st.kernel_ms_avg:.3f} ms, windows {st.windows}, "
@@ -125,26 +182,68 @@ def main():
         b.close()
         return ms, st, res
 
-    ms, st, res = measure("plain", api.params(W=w.W, O=w.O, k=w.k, mode="plain"))
+    def summary(batch, ms, st, same=None, ref_ms=None):
+        d = dict(alignments_per_s=round(batch.npairs / (ms / 1e3), 1), ms_per_step=round(ms, 4),
+                 kernel_ms=round(st.kernel_ms_avg, 4), fallback_windows=int(st.fallback_windows),
+                 rows_budgeted=int(st.rows_budgeted), lane_steps=int(st.lane_steps),
+                 t64ops=round(st.ops_alg / (st.kernel_ms_avg / 1e3) / 1e12, 4))
+        if same is not None:
+            d["identical_to_plain"] = same
+        if ref_ms is not None:
+            d["speedup_vs_plain"] = round(ref_ms / ms, 3)
+        return d
+
+    w = synth.WORKLOADS[args.workload]
+    log(f"[bench] generating {args.workload} ({w.npairs} pairs)")
+    t = time.perf_counter()
+    batch = synth.make_batch(args.workload)
+    log(f"[bench] generated in {time.perf_counter() - t:.1f}s: {batch.pat.size} + {batch.txt.size} bases")
+
+    ms, st, res = measure(batch, "plain", api.params(W=w.W, O=w.O, k=w.k, mode="plain"), args.steps, args.warmup)
     variants = {}
     if not args.no_variants:
-        fms, fst, fres = measure("fixed", api.params(W=w.W, O=w.O, k=w.k, mode="fixed", fixed_rows=args.fixed_rows,
-                                                     slots=8))
-        same = same_output(fres, res)
-        variants[f"fixed_{args.fixed_rows}_rows"] = dict(
-            alignments_per_s=round(batch.npairs / (fms / 1e3), 1), ms_per_step=round(fms, 4),
-            kernel_ms=round(fst.kernel_ms_avg, 4), fallback_windows=int(fst.fallback_windows),
-            t64ops=round(fst.ops_alg / (fst.kernel_ms_avg / 1e3) / 1e12, 4),
-            identical_to_plain=same, speedup_vs_plain=round(ms / fms, 3))
-        if os.path.exists(WEIGHTS):
-            ctx.load_model(WEIGHTS)
-            lms, lst, lres = measure("learned", api.params(W=w.W, O=w.O, k=w.k, mode="learned", slots=8, tau=0.9))
-            same = same_output(lres, res)
-            variants["learned"] = dict(
-                alignments_per_s=round(batch.npairs / (lms / 1e3), 1), ms_per_step=round(lms, 4),
-                kernel_ms=round(lst.kernel_ms_avg, 4), fallback_windows=int(lst.fallback_windows),
-                t64ops=round(lst.ops_alg / (lst.kernel_ms_avg / 1e3) / 1e12, 4),
-                identical_to_plain=same, speedup_vs_plain=round(ms / lms, 3))
+        fms, fst, fres = measure(batch, "fixed", api.params(W=w.W, O=w.O, k=w.k, mode="fixed",
+                                                            fixed_rows=args.fixed_rows), args.steps, args.warmup)
+        variants[f"fixed_{args.fixed_rows}_rows"] = summary(batch, fms, fst, same_output(fres, res), ms)
+        if have_model:
+            lms, lst, lres = measure(batch, "learned", api.params(W=w.W, O=w.O, k=w.k, mode="learned"),
+                                     args.steps, args.warmup)
+            variants["learned"] = summary(batch, lms, lst, same_output(lres, res), ms)
+
+    workloads = {}
+    if not args.no_workloads:
+        # per-pair edit rate 5-15%: learned budget vs plain
+        name = "mixed_10kbp"
+        wb = synth.make_batch(name)
+        ww = synth.WORKLOADS[name]
+        pms, pst, pres = measure(wb, f"{name} plain", api.params(W=ww.W, O=ww.O, k=ww.k, mode="plain"), 5, 1)
+        entry = {"pairs": wb.npairs, "plain": summary(wb, pms, pst)}
+        if have_model:
+            lms, lst, lres = measure(wb, f"{name} learned", api.params(W=ww.W, O=ww.O, k=ww.k, mode="learned"), 5, 1)
+            entry["learned"] = summary(wb, lms, lst, same_output(lres, pres), pms)
+        workloads[name] = entry
+        del wb
+        # uneven lengths: autotuned launch shape, one hipGraph-captured launch per step
+        name = "uneven_lognormal"
+        log(f"[bench] generating {name}")
+        wb = synth.make_batch(name)
+        ww = synth.WORKLOADS[name]
+        entry = {"pairs": wb.npairs, "bases": int(wb.pat.size)}
+        ref = None
+        for mode in (("plain", "learned") if have_model else ("plain",)):
+            best, trials = autotune.tune(ctx, wb, ww.W, ww.O, ww.k, mode=mode, reps=1, cache_path=None, log=log)
+            gms, gst, gres = measure(wb, f"{name} {mode} graph {best}",
+                                     api.params(W=ww.W, O=ww.O, k=ww.k, mode=mode, graph=True, **best), 5, 1)
+            e = summary(wb, gms, gst, None if ref is None else same_output(gres, ref[1]),
+                        None if ref is None else ref[0])
+            e["autotuned"] = best
+            e["graph"] = True
+            e["candidates"] = len(trials)
+            entry[mode] = e
+            if ref is None:
+                ref = (gms, gres)
+        workloads[name] = entry
+        del wb
 
     achieved = st.ops_alg / (st.kernel_ms_avg / 1e3) / 1e12
     out = {
@@ -160,14 +259,16 @@ def main():
         "vs_baseline": None,
         "dtype": "u64",
         "data": "synthetic",
-        "config": {"workload": args.workload, "pairs": batch.npairs, "pattern_length": str(w.length),
-                   "edit_rate": str(w.rate), "W": w.W, "O": w.O, "k": w.k, "mode": "plain"},
+        "config": {"workload": args.workload, "pairs": batch.npairs, "pattern_length": spec(w.length),
+                   "edit_rate": spec(w.rate), "W": w.W, "O": w.O, "k": w.k, "mode": "plain"},
         "gbitops_per_s": round(achieved * 1e3, 2),
         "roofline": {"bound": "alu", "achieved": round(achieved, 4), "peak": round(PEAK_T64OPS, 3),
-                     "unit": "T 64-bit op/s", "frac": round(achieved / PEAK_T64OPS, 5), "traffic": None,
-                     "kernel": "align_kernel", "kernel_ms": round(st.kernel_ms_avg, 4),
+                     "unit": "T 64-bit op/s", "frac": round(achieved / PEAK_T64OPS, 5),
+                     "traffic": measured_traffic("align_kernel_plain"),
+                     "kernel": "align_kernel<false>", "kernel_ms": round(st.kernel_ms_avg, 4),
                      "ops_alg_per_launch": int(st.ops_alg), "windows_per_launch": int(st.windows)},
         "variants": variants,
+        "workloads": workloads,
     }
     if not args.no_cpu:
         log("[bench] CPU oracle baseline")

@@ -113,8 +113,9 @@ const char* scg_strerror(int code);
  * the call and the runtime's message.  Static per-thread storage. */
 const char* scg_last_hip_error(void);
 
-/* Default parameters: W=64, O=24, k=64, plain mode, automatic launch shape,
- * yield_chars = 1280. */
+/* Default parameters: W=64, O=24, k=64, plain mode, automatic launch shape
+ * (slots = 1 in plain mode, 4 with a row budget; the occupancy maximum of
+ * wavefronts per CU), fixed_rows = 15, tau = 0.8, yield_chars = 1280. */
 void scg_params_default(scg_params* p);
 
 /* Create a context on HIP device `device`.  *out receives the context; the

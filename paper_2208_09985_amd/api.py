@@ -32,7 +32,7 @@ def _stream_ptr(stream) -> ctypes.c_void_p:
     return ctypes.c_void_p(stream.cuda_stream)
 
 
-def params(W=64, O=24, k=64, mode="plain", slots=0, waves_per_cu=0, order="input", fixed_rows=15, tau=0.9,
+def params(W=64, O=24, k=64, mode="plain", slots=0, waves_per_cu=0, order="input", fixed_rows=None, tau=None,
            graph=False, yield_chars=None) -> L.Params:
     p = L.Params()
     L.load().scg_params_default(ctypes.byref(p))
@@ -40,7 +40,10 @@ def params(W=64, O=24, k=64, mode="plain", slots=0, waves_per_cu=0, order="input
     p.mode = {"plain": L.MODE_PLAIN, "learned": L.MODE_LEARNED, "fixed": L.MODE_FIXED}[mode]
     p.slots, p.waves_per_cu = slots, waves_per_cu
     p.order = {"input": L.ORDER_INPUT, "longest_first": L.ORDER_LONGEST_FIRST}[order]
-    p.fixed_rows, p.tau = fixed_rows, tau
+    if fixed_rows is not None:
+        p.fixed_rows = fixed_rows
+    if tau is not None:
+        p.tau = tau
     p.flags = L.FLAG_GRAPH if graph else 0
     if yield_chars is not None:
         p.yield_chars = yield_chars

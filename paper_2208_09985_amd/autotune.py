@@ -33,7 +33,7 @@ DEFAULT_CACHE = os.path.join(os.path.expanduser("~"), ".cache", "scrooge_mi355x"
 SPACE = {
     "plain": {"slots": [1, 2], "waves_per_cu": [0], "order": ["input", "longest_first"]},
     "fixed": {"slots": [2, 4, 6, 8], "waves_per_cu": [0], "order": ["input"], "fixed_rows": [7, 11, 15, 23]},
-    "learned": {"slots": [2, 4, 6, 8], "waves_per_cu": [0], "order": ["input"], "tau": [0.5, 0.6, 0.7, 0.8, 0.9]},
+    "learned": {"slots": [2, 4, 6], "waves_per_cu": [0], "order": ["input"], "tau": [0.7, 0.8, 0.9]},
 }
 
 

@@ -221,7 +221,7 @@ void scg_params_default(scg_params* p) {
     p->mode = SCG_MODE_PLAIN;
     p->order = SCG_ORDER_INPUT;
     p->fixed_rows = 15;
-    p->tau = 0.9f;
+    p->tau = 0.8f;
     p->yield_chars = 1280;
 }
 
@@ -414,7 +414,7 @@ int scg_batch_create(scg_ctx* c, const scg_params* params, int32_t npairs, const
     // host vectors die at return: wait for the copies
     if ((rc = from_hip(hipStreamSynchronize(s)))) return fail(rc);
     // launch shape
-    b->ns = params->slots > 0 ? params->slots : (params->mode == SCG_MODE_PLAIN ? 1 : 8);
+    b->ns = params->slots > 0 ? params->slots : (params->mode == SCG_MODE_PLAIN ? 1 : 4);
     b->lds = align_lds_bytes(params->W - params->O + 1, b->ns);
     int per_cu = align_max_blocks_per_cu(b->lds, params->mode == SCG_MODE_LEARNED);
     if (params->waves_per_cu > 0) per_cu = std::min(per_cu, params->waves_per_cu);
