@@ -75,6 +75,13 @@ enum { SCG_ORDER_INPUT = 0, SCG_ORDER_LONGEST_FIRST = 1 };
 enum { SCG_WHERE_HOST = 0, SCG_WHERE_DEVICE = 1 };
 enum { SCG_FLAG_GRAPH = 1 };  /* replay the batch's launches from a captured hipGraph */
 
+/* which fused kernel aligns the batch (same results, different mappings) */
+enum {
+    SCG_KERNEL_AUTO = 0,     /* column blocks in plain mode, error rows with a row budget     */
+    SCG_KERNEL_ROWS = 1,     /* lanes are error rows; windows packed as lane segments          */
+    SCG_KERNEL_COLUMNS = 2   /* 16 windows per wavefront, 4 lanes x 16 text columns per window */
+};
+
 typedef struct {
     int32_t W, O, k;        /* window size, overlap, edit budget per window            */
     int32_t mode;           /* SCG_MODE_*                                              */
@@ -86,6 +93,7 @@ typedef struct {
     int32_t flags;          /* SCG_FLAG_*                                              */
     int32_t yield_chars;    /* a pair returns to the queue after advancing this many   */
                             /* pattern characters (0 = never; else >= W-O)             */
+    int32_t kernel;         /* SCG_KERNEL_*                                            */
 } scg_params;
 
 typedef struct {

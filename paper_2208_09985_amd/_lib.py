@@ -17,6 +17,7 @@ MODE_PLAIN, MODE_LEARNED, MODE_FIXED = 0, 1, 2
 ORDER_INPUT, ORDER_LONGEST_FIRST = 0, 1
 WHERE_HOST, WHERE_DEVICE = 0, 1
 FLAG_GRAPH = 1
+KERNEL_AUTO, KERNEL_ROWS, KERNEL_COLUMNS = 0, 1, 2
 NFEATURES = 16
 
 EXPORTED = [
@@ -32,7 +33,7 @@ class Params(ctypes.Structure):
         ("W", ctypes.c_int32), ("O", ctypes.c_int32), ("k", ctypes.c_int32),
         ("mode", ctypes.c_int32), ("slots", ctypes.c_int32), ("waves_per_cu", ctypes.c_int32),
         ("order", ctypes.c_int32), ("fixed_rows", ctypes.c_int32), ("tau", ctypes.c_float),
-        ("flags", ctypes.c_int32), ("yield_chars", ctypes.c_int32),
+        ("flags", ctypes.c_int32), ("yield_chars", ctypes.c_int32), ("kernel", ctypes.c_int32),
     ]
 
 

@@ -33,7 +33,7 @@ def _stream_ptr(stream) -> ctypes.c_void_p:
 
 
 def params(W=64, O=24, k=64, mode="plain", slots=0, waves_per_cu=0, order="input", fixed_rows=None, tau=None,
-           graph=False, yield_chars=None) -> L.Params:
+           graph=False, yield_chars=None, kernel="auto") -> L.Params:
     p = L.Params()
     L.load().scg_params_default(ctypes.byref(p))
     p.W, p.O, p.k = W, O, k
@@ -47,6 +47,7 @@ def params(W=64, O=24, k=64, mode="plain", slots=0, waves_per_cu=0, order="input
     p.flags = L.FLAG_GRAPH if graph else 0
     if yield_chars is not None:
         p.yield_chars = yield_chars
+    p.kernel = {"auto": L.KERNEL_AUTO, "rows": L.KERNEL_ROWS, "columns": L.KERNEL_COLUMNS}[kernel]
     return p
 
 

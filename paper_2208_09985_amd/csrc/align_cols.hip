@@ -1,0 +1,546 @@
+// Fused, persistent windowed GenASM-DC + GenASM-TB kernel for gfx950,
+// column-block mapping.
+//
+// Mapping (one wavefront = one workgroup, 64 lanes):
+//   * A wavefront holds NG windows of NG different pairs (NG = 4, 8 or 16),
+//     one per group of L = 64/NG consecutive lanes.  Lane q of a group owns
+//     the CB = NG text columns CB*q .. CB*q+CB-1 of its window and keeps, for
+//     each of them, the bitvector of the current error row and the column's
+//     pattern-match mask (two VGPRs each).  Fewer windows per wavefront give
+//     more wavefronts for the same number of pairs, at the price of a longer
+//     skew (L-1 steps per window).
+//   * The group computes the rows d = 0, 1, 2, ... of Algorithm 1 one after
+//     the other (Section 2.2.1).  Inside a row the dependence runs from the
+//     text end toward column 0, so the L lanes are skewed by one step: lane q
+//     computes row d at step d + L-1 - q.  The value a lane needs from the
+//     columns to its right (row d and row d-1 of column CB*q+CB) arrives from
+//     lane q+1 through one DPP wave_shl:1 per 32-bit half; lane L-1 takes the
+//     window's initial column (Section 2.2.1) instead.  Text columns at
+//     or beyond n_w carry the initial column too, because their match mask is
+//     empty, so windows shorter than 64 need no special case.
+//   * Bitvectors are kept as the complement Z = ~R in LSB-first order (bit j =
+//     pattern position j); the update of Algorithm 1 becomes
+//         Z[i][d] = ((Z[i][d-1] | Z[i+1][d-1]) >> 1 | top) | Z[i+1][d-1]
+//                 | ((Z[i+1][d] >> 1 | top) & EQ[text[i]])
+//     ten 32-bit operations per entry.  Before a lane's first row its inputs
+//     are zero and both shifted-in bits are off, so ramp steps leave it zero.
+//   * Early termination (Section 2.4.3): lane 0 of a group holds column 0;
+//     the first row whose entry has the msb of R clear is d_w, found by one
+//     ballot per step.  A wavefront's DC pass ends when no group is still
+//     computing.
+//   * Stored entries (Section 2.4.1, entries not edges; Section 2.4.2, only
+//     columns 0..W-O are read by traceback) go to a per-group region of
+//     global memory, [row][column] with a row stride that is a multiple of
+//     CB; each storing lane writes its CB columns with 16-byte stores.
+//   * Traceback runs in lane 0 of every finished group, all groups of the
+//     wavefront together: match runs are skipped with an XOR of the 2-bit
+//     planes and a trailing-zero count, and each edit step reads row d-1 at
+//     columns i and i+1.
+//   * Row budgets: a pass ends when every window it waits for has found
+//     d_w.  Plain mode waits for every window (rows 0..k_w at most).  Fixed
+//     mode waits for a window up to fixed_rows rows, learned mode up to the
+//     predicted budget (and not at all for a window predicted to need more
+//     than 16 rows).  A window over its budget keeps computing in its lanes,
+//     with all rows, through the following passes, and is traced back when
+//     its d_w is found; rows <= d never depend on rows > d, so the result is
+//     bit-identical.
+//   * Pairs are taken from the global queue shared with the row-lane kernel;
+//     a pair that has advanced yield_chars pattern characters saves its
+//     state and goes back to the queue between windows.
+#include "predictor.h"
+
+namespace {
+
+constexpr int kMaxGroups = 16;     // windows per wavefront, at most
+constexpr int kStoredRows = 64;    // rows 0..63 are kept for traceback
+constexpr uint32_t kDppWaveShl1 = 0x130;
+
+// A group is RUN while the pass waits for it, OVER once it has used its row
+// budget without finding d_w (it keeps computing, but the pass no longer
+// waits for it), DONE when d_w is known (or no row up to k_w has it), TB
+// while its traceback runs (possibly over several rounds).
+enum : int { G_EMPTY = 0, G_RUN = 1, G_DONE = 2, G_OVER = 3, G_TB = 4 };
+constexpr int kTbEvents = 24;      // traceback events (match runs or edit steps) per round
+constexpr int kWaitRows = 16;      // learned mode: largest predicted budget a pass waits for
+enum : int { CMD_NONE = 0, CMD_FRESH = 1, CMD_RESUME = 2 };
+
+struct GroupRec {      // LDS: what the slot lane tells its group at set-up
+    uint64_t plo, phi, tlo, thi;   // window planes (pattern at p0, text at t0)
+    int32_t m_w, n_w;
+    int32_t limit;     // rows 0..limit-1 of column 0 may be computed this pass
+    int32_t full;      // rows of the whole window
+    int32_t cmd;
+    int32_t pad;
+};
+
+__device__ __forceinline__ uint32_t from_upper_lane(uint32_t x) {
+    // lane l receives lane l+1's value; lane 63 receives 0
+    return (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, kDppWaveShl1, 0xF, 0xF, true);
+}
+
+// Z of the initial column (i = n_w): bit j set iff m_w - j <= d
+__device__ __forceinline__ uint64_t z_init(int mw, int d) {
+    const int s = mw - d;
+    return s <= 0 ? ~0ull : (s >= 64 ? 0ull : (~0ull << s));
+}
+
+__device__ __forceinline__ int zbit(uint64_t z, int p) { return p >= 64 ? 1 : (int)((z >> p) & 1ull); }
+
+// Append `len` (>= 0) operations `op` to a pair's run list, merging equal
+// neighbours; len == 0 changes nothing.
+__device__ __forceinline__ void emit_run(int op, int len, int& cur_op, int& cur_len, int& nruns,
+                                         uint32_t* __restrict__ runs, int64_t roff, int64_t rcap) {
+    const bool same = cur_op == op;
+    const bool flush = !same && cur_len > 0 && len > 0;
+    if (flush && nruns < rcap) runs[roff + nruns] = ((uint32_t)cur_len << 2) | (uint32_t)cur_op;
+    nruns += flush ? 1 : 0;
+    cur_len = len == 0 ? cur_len : (same ? cur_len + len : len);
+    cur_op = len == 0 ? cur_op : op;
+}
+
+// One error row of the lane's CB columns: two VGPRs per column.
+template <int CB>
+struct RowRegs {
+    uint32_t lo[CB], hi[CB];
+};
+
+// Row d of columns CB*q+CB-1 .. CB*q, in place over row d-1.  (nl, nh) is row d
+// and (sl, sh) row d-1 of column CB*q+CB; tm and cin are the bits shifted in
+// by the M term and by the I/S terms.  The I, S and D terms need only row
+// d-1, so a first pass (ascending columns, each column still finds its right
+// neighbour's old value) leaves ((Z[t] | Z[t+1]) >> 1 | cin) | Z[t+1] in place;
+// the M term needs row d of the right neighbour, so a second pass runs from
+// column CB*q+CB-1 down and ORs it in.
+template <int CB>
+__device__ __forceinline__ void dc_row(RowRegs<CB>& P, const RowRegs<CB>& eq, uint32_t nl, uint32_t nh, uint32_t sl,
+                                       uint32_t sh, uint32_t tm, uint32_t cin) {
+    // first pass as register-tied assembly: each column is rewritten in its
+    // own registers (left to itself the compiler rotates the whole row
+    // through new registers and copies it back every step)
+#pragma unroll
+    for (int t = 0; t < CB; ++t) {
+        const uint32_t xl = t < CB - 1 ? P.lo[t + 1] : sl;
+        const uint32_t xh = t < CB - 1 ? P.hi[t + 1] : sh;
+        uint32_t ul, uh;
+        asm("v_or_b32 %[ul], %[pl], %[xl]\n\t"
+            "v_or_b32 %[uh], %[ph], %[xh]\n\t"
+            "v_alignbit_b32 %[pl], %[uh], %[ul], 1\n\t"
+            "v_alignbit_b32 %[ph], %[cin], %[uh], 1\n\t"
+            "v_or_b32 %[pl], %[pl], %[xl]\n\t"
+            "v_or_b32 %[ph], %[ph], %[xh]"
+            : [pl] "+v"(P.lo[t]), [ph] "+v"(P.hi[t]), [ul] "=&v"(ul), [uh] "=&v"(uh)
+            : [xl] "v"(xl), [xh] "v"(xh), [cin] "v"(cin));
+    }
+#pragma unroll
+    for (int t = CB - 1; t >= 0; --t) {
+        const uint32_t bl = __builtin_amdgcn_alignbit(nh, nl, 1);
+        const uint32_t bh = __builtin_amdgcn_alignbit(tm, nh, 1);
+        P.lo[t] = (bl & eq.lo[t]) | P.lo[t];
+        P.hi[t] = (bh & eq.hi[t]) | P.hi[t];
+        nl = P.lo[t];
+        nh = P.hi[t];
+    }
+}
+
+template <bool LEARNED, int CB>
+__global__ __launch_bounds__(64) void cols_kernel(const AlignArgs a) {
+    constexpr int NG = CB;          // windows per wavefront
+    constexpr int L = 64 / NG;      // lanes per window
+    __shared__ GroupRec grec[NG];
+    const int lane = threadIdx.x;
+    const int g = lane / L, q = lane % L;
+    const bool slot = q == 0;
+    const int cap = a.cap;
+    const int stride = a.dstride;
+    uint64_t* const gdent = a.dent + ((size_t)blockIdx.x * NG + g) * (size_t)(kStoredRows * stride);
+    const bool storer = CB * q < stride;
+
+    if (lane < NG) grec[lane] = GroupRec{0, 0, 0, 0, 0, 0, 0, 0, CMD_NONE, 0};
+
+    // ---- slot-lane state (lanes with q == 0) ----
+    int pair = -1, p0 = 0, t0 = 0, m = 0, n = 0, edits = 0, nruns = 0, cur_op = 0, cur_len = 0, p0_take = 0;
+    int mw = 0, nw = 0, kw = 0;
+    int64_t roff = 0, rcap = 0, pending = -1;
+    int polled = 0;
+    bool exhausted = !slot;
+    unsigned long long c_windows = 0, c_ops = 0, c_fallback = 0, c_rows = 0, c_err = 0, c_yield = 0;
+    int tb_i = 0, tb_j = 0, tb_d = 0, tb_e = 0, tb_bad = 0;   // slot lane: traceback position and edits
+    unsigned long long c_lane_steps = 0, c_rounds = 0;
+
+    // ---- lane state: current row of the lane's 16 columns, their match masks ----
+    RowRegs<CB> A, E;
+    for (int t = 0; t < CB; ++t) A.lo[t] = A.hi[t] = E.lo[t] = E.hi[t] = 0;
+    uint32_t nbslo = 0, nbshi = 0;     // row d-1 of column CB*q+CB
+    uint32_t zrlo = 0, zrhi = 0;       // initial column at the lane's next row (used by q == L-1)
+    int dl = 0;                        // row this lane computes at the next step
+    int gst = G_EMPTY;                 // group state, identical in the group's four lanes
+    int limit = 0, full = 0, dw = -1;
+    uint32_t over_events = 0;
+
+    for (;;) {
+        // ---- 1. slot lanes take pairs from the queue ----
+        if (!exhausted && pair < 0) {
+            if (pending < 0) pending = (int64_t)atomicAdd(&a.qctl[0], 1u);
+            if (pending >= a.qcap) {
+                exhausted = true;
+            } else {
+                polled = __hip_atomic_load(&a.ring[pending], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                if (polled != 0) {
+                    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+                    const bool fresh = pending < a.npairs;
+                    const int pid = polled - 1;
+                    pending = -1;
+                    polled = 0;
+                    const int pm = a.plen[pid], pn = a.tlen[pid];
+                    if (fresh && (a.bad[pid] || pm == 0)) {
+                        const bool bad = a.bad[pid] != 0;
+                        a.edits[pid] = bad ? -1 : 0;
+                        a.text_end[pid] = bad ? -1 : 0;
+                        a.status[pid] = bad ? 2 : 0;
+                        a.n_runs[pid] = 0;
+                        atomicAdd(&a.qctl[2], 1u);
+                    } else {
+                        pair = pid;
+                        m = pm;
+                        n = pn;
+                        if (fresh) {
+                            p0 = 0; t0 = 0; edits = 0; nruns = 0; cur_op = 0; cur_len = 0;
+                        } else {
+                            const int32_t* st = a.pstate + 8 * (int64_t)pid;
+                            p0 = st[0]; t0 = st[1]; edits = st[2]; nruns = st[3]; cur_op = st[4]; cur_len = st[5];
+                        }
+                        p0_take = p0;
+                        roff = a.runs_off[pid];
+                        rcap = a.runs_off[pid + 1] - roff;
+                    }
+                }
+            }
+        }
+
+        // ---- 2. slot lanes start windows (or resume paused ones) ----
+        if (slot) {
+            GroupRec& r = grec[g];
+            if (gst == G_EMPTY && pair >= 0) {
+                mw = min(a.W, m - p0);
+                nw = min(a.W, n - t0);
+                kw = min(a.k, mw);
+                const int rows_full = (kw == mw) ? mw : kw + 1;   // row m_w is implicit: D(0,0) <= m_w
+                uint64_t plo, phi, tlo = 0, thi = 0;
+                load_window(a.pplanes + a.pword[pair], p0, plo, phi);
+                if (nw > 0) load_window(a.tplanes + a.tword[pair], t0, tlo, thi);
+                r.plo = plo;
+                r.phi = phi;
+                r.tlo = tlo;
+                r.thi = thi;
+                r.m_w = mw;
+                r.n_w = nw;
+                r.full = rows_full;
+                r.limit = a.mode == 2 ? min(a.fixed_rows, rows_full) : rows_full;
+                r.cmd = CMD_FRESH;
+            } else {
+                r.cmd = CMD_NONE;
+            }
+        }
+        __syncthreads();
+
+        // ---- 3. learned row budget of fresh windows: features -> MLP (MFMA) ----
+        if constexpr (LEARNED) {
+            MlpRegs mlp;
+            mlp_load_packed(mlp, a.model.operands, lane);
+            const int s = lane & 15, fg = lane >> 4;
+            const GroupRec rs = grec[s < NG ? s : 0];
+            const WinPlanes o{rs.plo, rs.phi, rs.tlo, rs.thi, rs.m_w, rs.n_w};
+            half4_t x4;
+            for (int e = 0; e < 4; ++e) x4[e] = feature_to_input(window_feature(o, 4 * fg + e));
+            half4_t hid[4];
+            const float4_t logit = mlp_tile_forward(mlp, x4, hid);
+            __syncthreads();
+            if (lane < NG && rs.cmd == CMD_FRESH) {
+                // lane s < 16 holds classes 0..3 of group s
+                const int C = a.model.C;
+                float mx = logit[0];
+                for (int c = 1; c < C; ++c) mx = fmaxf(mx, logit[c]);
+                float p[4], tot = 0.f;
+                for (int c = 0; c < C; ++c) {
+                    p[c] = __expf(logit[c] - mx);
+                    tot += p[c];
+                }
+                int cls = C - 1;
+                float cum = 0.f;
+                for (int c = 0; c < C; ++c) {
+                    cum += p[c];
+                    if (cum >= a.model.tau * tot) {
+                        cls = c;
+                        break;
+                    }
+                }
+                // the pass waits for a window only up to its predicted budget, and
+                // not at all for one predicted to need many rows
+                const int br = a.model.budget_rows[cls];
+                grec[lane].limit = br <= kWaitRows ? max(1, min(br, rs.full)) : 1;
+            }
+            __syncthreads();
+        }
+
+        // ---- 4. every lane applies its group's command ----
+        {
+            const GroupRec r = grec[g];
+            if (r.cmd == CMD_FRESH) {
+                const uint64_t beyond = r.m_w >= 64 ? 0ull : (~0ull << r.m_w);
+                const uint32_t tql = (uint32_t)(r.tlo >> (CB * q)), tqh = (uint32_t)(r.thi >> (CB * q));
+                const int ncols = min(max(r.n_w - CB * q, 0), CB);   // this lane's columns inside the text window
+#pragma unroll
+                for (int t = 0; t < CB; ++t) {
+                    const uint64_t sl = ((tql >> t) & 1u) ? r.plo : ~r.plo;
+                    const uint64_t sh = ((tqh >> t) & 1u) ? r.phi : ~r.phi;
+                    const uint64_t e = (t < ncols ? (sl & sh) : 0ull) | beyond;
+                    E.lo[t] = (uint32_t)e;
+                    E.hi[t] = (uint32_t)(e >> 32);
+                    A.lo[t] = 0;
+                    A.hi[t] = 0;
+                }
+                nbslo = nbshi = 0;
+                const uint64_t zr = z_init(r.m_w, 0);
+                zrlo = (uint32_t)zr;
+                zrhi = (uint32_t)(zr >> 32);
+                dl = q - (L - 1);
+                limit = r.limit;
+                full = r.full;
+                dw = -1;
+                gst = G_RUN;
+            }
+        }
+        // with no window to wait for, wait for the ones over budget
+        if (__ballot(gst == G_RUN) == 0 && gst == G_OVER) gst = G_RUN;
+
+        const bool any_run = __ballot(gst == G_RUN) != 0;
+        if (!any_run && __ballot(gst == G_TB) == 0) {
+            // nothing to compute: leave once every pair is finished or no slot
+            // can ever receive one; otherwise wait for yielded pairs
+            const bool waiting = !exhausted && pair < 0;
+            if (__ballot(waiting) == 0) break;
+            if (__hip_atomic_load(&a.qctl[2], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) >= (uint32_t)a.npairs) break;
+            __builtin_amdgcn_s_sleep(16);
+            continue;
+        }
+
+        // ---- 5. DC pass: one row of every running window per step ----
+        int steps = 0;
+        while (any_run) {
+            // every lane computes; only lanes of running windows store and count
+            const bool computing = gst == G_RUN || gst == G_OVER;
+            const uint32_t tm = dl >= 0 ? 1u : 0u;    // the M term shifts in a 1 from the lane's first row on
+            const uint32_t cin = dl >= 1 ? 1u : 0u;   // the I/S terms from its second row on
+            uint32_t nlo = from_upper_lane(A.lo[0]);
+            uint32_t nhi = from_upper_lane(A.hi[0]);
+            if (q == L - 1) {
+                nlo = zrlo;
+                nhi = zrhi;
+            }
+            dc_row(A, E, nlo, nhi, nbslo, nbshi, tm, cin);
+            nbslo = nlo;
+            nbshi = nhi;
+            {   // initial column, one row further
+                const uint32_t zl = __builtin_amdgcn_alignbit(zrhi, zrlo, 1);
+                const uint32_t zh = __builtin_amdgcn_alignbit(1u, zrhi, 1);
+                zrlo = zl;
+                zrhi = zh;
+            }
+            // keep the row for traceback
+            if (computing && storer && dl >= 0 && dl < kStoredRows) {
+                uint4* row = reinterpret_cast<uint4*>(gdent + (size_t)dl * stride + CB * q);
+#pragma unroll
+                for (int t = 0; t < CB; t += 2) row[t >> 1] = uint4{A.lo[t], A.hi[t], A.lo[t + 1], A.hi[t + 1]};
+            }
+            // early termination: column 0 of row d has the msb of R clear
+            const uint64_t hb = __ballot(slot && computing && dl >= 0 && (A.lo[0] & 1u));
+            if (computing) {
+                const int d0 = dl - q;   // row of column 0 computed at this step
+                if ((hb >> (lane - q)) & 1ull) {
+                    gst = G_DONE;
+                    dw = d0;
+                } else if (d0 >= full - 1) {
+                    gst = G_DONE;        // dw = -1: no distance within rows 0..k_w
+                } else if (gst == G_RUN && d0 >= limit - 1) {
+                    gst = G_OVER;        // over budget: no longer waited for
+                    over_events += 1;
+                }
+            }
+            dl += 1;
+            steps += 1;
+            if (__ballot(gst == G_RUN) == 0) break;
+        }
+        c_lane_steps += 64ull * (unsigned long long)steps;
+        c_rounds += 1;
+        // the group's stored rows are read by its slot lane
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+        __syncthreads();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
+
+        // ---- 6. traceback of finished windows, advance, output ----
+        // Finished windows start their traceback; every traceback in the
+        // wavefront then runs at most kTbEvents match runs / edit steps in
+        // this round and continues in the next one, so one long path does
+        // not hold the whole wavefront.
+        if (slot && gst == G_DONE) {
+            c_rows += (unsigned long long)(dw < 0 ? full : dw + 1);
+            tb_d = dw;
+            if (tb_d < 0 && kw == mw) tb_d = mw;   // no hit in rows 0..m_w-1: distance m_w
+            if (tb_d < 0) {
+                // no distance within k: the pair is not aligned
+                c_windows += 1;
+                c_ops += (unsigned long long)(kw + 1) + 2ull * nw + 7ull * nw * kw;
+                a.edits[pair] = -1;
+                a.text_end[pair] = -1;
+                a.status[pair] = 1;
+                a.n_runs[pair] = 0;
+                pair = -1;
+                atomicAdd(&a.qctl[2], 1u);
+                gst = G_EMPTY;
+            } else {
+                c_windows += 1;
+                c_ops += (unsigned long long)(tb_d + 1) + 2ull * nw + 7ull * nw * tb_d;
+                tb_i = tb_j = tb_e = tb_bad = 0;
+            }
+        }
+        if (gst == G_DONE) gst = G_TB;
+        if (__ballot(slot && gst == G_TB) != 0) {
+            const bool tracing = slot && gst == G_TB;
+            const GroupRec r = grec[g];
+            const int jlim = min(mw, cap);
+            bool fin = !tracing;
+            for (int ev = 0; ev < kTbEvents && __ballot(!fin) != 0; ++ev) {
+                if (!fin) {
+                    // match run at (ti, tj); characters past n_w never match
+                    const uint64_t x = ((r.thi >> tb_i) ^ (r.phi >> tb_j)) | ((r.tlo >> tb_i) ^ (r.plo >> tb_j));
+                    int L = x ? (int)__builtin_ctzll(x) : 64;
+                    L = min(L, min(nw - tb_i, min(jlim - tb_j, cap - tb_i)));
+                    L = max(L, 0);
+                    emit_run(0, L, cur_op, cur_len, nruns, a.runs, roff, rcap);
+                    tb_i += L;
+                    tb_j += L;
+                    fin = tb_j >= jlim || tb_i >= cap;
+                }
+                if (!fin) {
+                    // edit step: bits tj, tj+1 of row td-1 at columns ti and ti+1
+                    const int ti = tb_i, tj = tb_j, td = tb_d;
+                    const uint64_t* rowp = gdent + (size_t)(max(td, 1) - 1) * stride;
+                    const uint64_t v0 = rowp[min(ti, stride - 1)];
+                    const uint64_t v1 = rowp[min(ti + 1, stride - 1)];
+                    const uint64_t rc = z_init(mw, td - 1);
+                    const uint64_t za = ti < nw ? v0 : rc;        // Z[ti][td-1]
+                    const uint64_t zb = ti + 1 < nw ? v1 : rc;    // Z[ti+1][td-1]
+                    const int has_t = ti < nw;
+                    const int sb = has_t & zbit(zb, tj + 1);
+                    const int ib = zbit(za, tj + 1);
+                    const int db = has_t & zbit(zb, tj);
+                    tb_bad |= (td <= 0) | !(sb | ib | db);
+                    const int op = sb ? 1 : (ib ? 2 : 3);
+                    tb_i += op != 2;
+                    tb_j += op != 3;
+                    tb_d -= 1;
+                    tb_e += 1;
+                    emit_run(op, 1, cur_op, cur_len, nruns, a.runs, roff, rcap);
+                    fin = tb_j >= jlim || tb_i >= cap || tb_bad;
+                }
+            }
+            if (tracing && fin) {
+                // advance the pair past the traced characters
+                edits += tb_e;
+                p0 += tb_j;
+                t0 += tb_i;
+                gst = G_EMPTY;
+                if (tb_bad || p0 >= m) {
+                    if (cur_len > 0) {
+                        if (nruns < rcap) a.runs[roff + nruns] = ((uint32_t)cur_len << 2) | (uint32_t)cur_op;
+                        ++nruns;
+                    }
+                    const bool ok = !tb_bad && nruns <= rcap;
+                    if (!ok) c_err += 1;
+                    a.edits[pair] = ok ? edits : -1;
+                    a.text_end[pair] = ok ? t0 : -1;
+                    a.status[pair] = ok ? 0 : 3;
+                    a.n_runs[pair] = ok ? nruns : 0;
+                    pair = -1;
+                    atomicAdd(&a.qctl[2], 1u);
+                } else if (a.yield_chars > 0 && p0 - p0_take >= a.yield_chars) {
+                    // hand the pair back to the queue between windows
+                    const uint32_t tq = atomicAdd(&a.qctl[1], 1u);
+                    if ((int64_t)tq < a.qcap) {
+                        int32_t* st = a.pstate + 8 * (int64_t)pair;
+                        st[0] = p0; st[1] = t0; st[2] = edits; st[3] = nruns; st[4] = cur_op; st[5] = cur_len;
+                        st[6] = 0; st[7] = 0;
+                        __hip_atomic_store(&a.ring[tq], pair + 1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+                        pair = -1;
+                        c_yield += 1;
+                    }
+                }
+            }
+        }
+        // the group's four lanes learn that its traceback ended
+        {
+            const uint64_t tbm = __ballot(slot && gst == G_TB);
+            if (!((tbm >> (lane - q)) & 1ull) && gst == G_TB) gst = G_EMPTY;
+        }
+        // traceback's reads of the stored rows finish before the next pass overwrites them
+        __syncthreads();
+    }
+
+    // ---- counters ----
+    if (slot) {
+        c_fallback = over_events;
+        if (c_windows) atomicAdd(&a.stats[ST_WINDOWS], c_windows);
+        if (c_ops) atomicAdd(&a.stats[ST_OPS_ALG], c_ops);
+        if (c_fallback) atomicAdd(&a.stats[ST_FALLBACK], c_fallback);
+        if (c_rows) atomicAdd(&a.stats[ST_ROWS], c_rows);
+        if (c_err) atomicAdd(&a.stats[ST_ERRORS], c_err);
+        if (c_yield) atomicAdd(&a.stats[ST_YIELDS], c_yield);
+    }
+    if (lane == 0) {
+        atomicAdd(&a.stats[ST_LANE_STEPS], c_lane_steps);
+        atomicAdd(&a.stats[ST_ROUNDS], c_rounds);
+    }
+}
+
+}  // namespace
+
+int cols_dent_stride(int cap, int ng) {
+    const int cols = cap + 1 < 64 ? cap + 1 : 64;   // stored columns 0..min(cap, 63)
+    return (cols + ng - 1) / ng * ng;               // whole lanes of CB = ng columns
+}
+
+size_t cols_dent_bytes(int grid, int cap, int ng) {
+    return (size_t)grid * ng * kStoredRows * (size_t)cols_dent_stride(cap, ng) * sizeof(uint64_t);
+}
+
+template <bool LEARNED>
+static const void* cols_fn(int ng) {
+    switch (ng) {
+    case 4: return (const void*)cols_kernel<LEARNED, 4>;
+    case 8: return (const void*)cols_kernel<LEARNED, 8>;
+    default: return (const void*)cols_kernel<LEARNED, 16>;
+    }
+}
+
+int cols_max_blocks_per_cu(bool learned, int ng, size_t lds) {
+    int nb = 0;
+    const void* f = learned ? cols_fn<true>(ng) : cols_fn<false>(ng);
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, f, 64, lds) != hipSuccess) return 1;
+    return nb < 1 ? 1 : nb;
+}
+
+hipError_t launch_align_cols(const AlignArgs& a, int grid, int ng, size_t lds, hipStream_t s) {
+    const bool learned = a.mode == 1;
+#define SCG_COLS_LAUNCH(LRN, NGV) hipLaunchKernelGGL((cols_kernel<LRN, NGV>), dim3(grid), dim3(64), lds, s, a)
+    if (learned) {
+        if (ng == 4) SCG_COLS_LAUNCH(true, 4);
+        else if (ng == 8) SCG_COLS_LAUNCH(true, 8);
+        else SCG_COLS_LAUNCH(true, 16);
+    } else {
+        if (ng == 4) SCG_COLS_LAUNCH(false, 4);
+        else if (ng == 8) SCG_COLS_LAUNCH(false, 8);
+        else SCG_COLS_LAUNCH(false, 16);
+    }
+#undef SCG_COLS_LAUNCH
+    return hipGetLastError();
+}

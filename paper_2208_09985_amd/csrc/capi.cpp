@@ -54,6 +54,9 @@ struct scg_batch {
     int64_t qcap = 0;
     int32_t* pstate_d = nullptr;
     unsigned long long* stats_d = nullptr;
+    uint64_t* dent_d = nullptr;     // column-block kernel: stored rows per group
+    int dstride = 0;
+    bool cols = false;              // column-block kernel selected
     // launch shape
     int ns = 1;
     int grid = 1;
@@ -110,6 +113,7 @@ int check_params(const scg_params* p) {
     if (p->mode == SCG_MODE_FIXED && (p->fixed_rows < 1 || p->fixed_rows > 64)) return SCG_EINVAL;
     if (p->mode == SCG_MODE_LEARNED && !(p->tau > 0.f && p->tau <= 1.f)) return SCG_EINVAL;
     if (p->yield_chars != 0 && p->yield_chars < p->W - p->O) return SCG_EINVAL;
+    if (p->kernel < SCG_KERNEL_AUTO || p->kernel > SCG_KERNEL_COLUMNS) return SCG_EINVAL;
     return SCG_OK;
 }
 
@@ -122,7 +126,7 @@ void free_batch(scg_batch* b) {
             if (e) (void)hipEventDestroy(e);
     void* ptrs[] = {b->own_seq ? b->pat_d : nullptr, b->own_seq ? b->txt_d : nullptr, b->pat_off_d, b->txt_off_d,
                     b->pplanes, b->tplanes, b->pword_d, b->tword_d, b->plen_d, b->tlen_d, b->bad_d, b->order_d,
-                    b->runs_off_d, b->qctl_d, b->ring_d, b->pstate_d, b->stats_d};
+                    b->runs_off_d, b->qctl_d, b->ring_d, b->pstate_d, b->stats_d, b->dent_d};
     for (void* q : ptrs)
         if (q) (void)hipFree(q);
     delete b;
@@ -183,7 +187,12 @@ int enqueue_run(scg_batch* b, hipStream_t s, int32_t* edits, int32_t* text_end, 
     a.pstate = b->pstate_d;
     a.yield_chars = b->p.yield_chars;
     a.stats = b->stats_d;
-    if (b->npairs > 0) HIP_TRY(launch_align(a, b->grid, b->lds, s));
+    a.dent = b->dent_d;
+    a.dstride = b->dstride;
+    if (b->npairs > 0) {
+        if (b->cols) HIP_TRY(launch_align_cols(a, b->grid, b->ns, b->lds, s));
+        else HIP_TRY(launch_align(a, b->grid, b->lds, s));
+    }
     if (with_events) {
         HIP_TRY(hipEventRecord(ev[2], s));
         b->ring_next = (b->ring_next + 1) % scg_batch::kRing;
@@ -414,13 +423,33 @@ int scg_batch_create(scg_ctx* c, const scg_params* params, int32_t npairs, const
     // host vectors die at return: wait for the copies
     if ((rc = from_hip(hipStreamSynchronize(s)))) return fail(rc);
     // launch shape
-    b->ns = params->slots > 0 ? params->slots : (params->mode == SCG_MODE_PLAIN ? 1 : 4);
-    b->lds = align_lds_bytes(params->W - params->O + 1, b->ns);
-    int per_cu = align_max_blocks_per_cu(b->lds, params->mode == SCG_MODE_LEARNED);
+    // automatic: column blocks for plain mode, error-row lanes when windows
+    // start with a row budget (there lanes above the budget are saved)
+    b->cols = params->kernel == SCG_KERNEL_COLUMNS ||
+              (params->kernel == SCG_KERNEL_AUTO && params->mode == SCG_MODE_PLAIN);
+    const bool learned = params->mode == SCG_MODE_LEARNED;
+    int per_cu;
+    if (b->cols) {
+        // windows per wavefront: 4, 8 or 16; automatic = enough wavefronts to
+        // give every SIMD two of them
+        if (params->slots > 0) b->ns = params->slots <= 4 ? 4 : (params->slots <= 8 ? 8 : 16);
+        else b->ns = npairs >= 16 * c->num_cu ? 16 : (npairs >= 8 * c->num_cu ? 8 : 4);
+        b->lds = 0;
+        per_cu = cols_max_blocks_per_cu(learned, b->ns, b->lds);
+    } else {
+        b->ns = params->slots > 0 ? params->slots : (params->mode == SCG_MODE_PLAIN ? 1 : 4);
+        b->lds = align_lds_bytes(params->W - params->O + 1, b->ns);
+        per_cu = align_max_blocks_per_cu(b->lds, learned);
+    }
     if (params->waves_per_cu > 0) per_cu = std::min(per_cu, params->waves_per_cu);
     b->grid = std::max(1, per_cu * c->num_cu);
     const int64_t need = (npairs + b->ns - 1) / b->ns;   // more wavefronts than slots-worth of pairs idle
     if (b->grid > need) b->grid = (int)std::max<int64_t>(1, need);
+    if (b->cols && npairs > 0) {
+        const int cap = params->W - params->O;
+        b->dstride = cols_dent_stride(cap, b->ns);
+        if ((rc = dev_alloc(&b->dent_d, cols_dent_bytes(b->grid, cap, b->ns) / sizeof(uint64_t)))) return fail(rc);
+    }
     *out = b;
     return SCG_OK;
 }

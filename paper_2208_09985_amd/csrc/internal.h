@@ -72,6 +72,9 @@ struct AlignArgs {
     int32_t* pstate;              // per pair: p0, t0, edits, nruns, cur_op, cur_len, next_w, 0
     int32_t yield_chars;          // a pair yields after advancing this many pattern chars (<= 0: never)
     unsigned long long* stats;    // ST_COUNT counters
+    // column-block kernel: stored rows of every group, [grid][16][64][dstride] u64
+    uint64_t* dent;
+    int32_t dstride;
 };
 
 // launchers (defined in the .hip files)
@@ -82,6 +85,10 @@ hipError_t launch_pack(const uint8_t* seq, const int64_t* off, const int64_t* wo
 hipError_t launch_align(const AlignArgs& a, int grid, size_t lds_bytes, hipStream_t s);
 size_t align_lds_bytes(int ccols, int ns);
 int align_max_blocks_per_cu(size_t lds_bytes, bool learned);
+hipError_t launch_align_cols(const AlignArgs& a, int grid, int ng, size_t lds, hipStream_t s);
+int cols_dent_stride(int cap, int ng);
+size_t cols_dent_bytes(int grid, int cap, int ng);
+int cols_max_blocks_per_cu(bool learned, int ng, size_t lds);
 hipError_t launch_features(const Plane2* pplanes, const Plane2* tplanes, const int64_t* pword,
                            const int64_t* tword, const int32_t* plen, const int32_t* tlen, int32_t npairs,
                            int32_t W, int32_t nwin, const int32_t* windows, uint16_t* features, hipStream_t s);

@@ -130,20 +130,24 @@ def test_learned_mode_is_bit_exact(ctx, model_path):
         b = synth.make_batch(name, n)
         ref = oracle.align_batch(b, 64, 24, 64)
         for tau in (0.5, 0.9, 0.99):
-            log(f"[learned] {name} tau={tau}")
-            compare(b, api.align_batch(ctx, b, mode="learned", tau=tau), ref, f"{name} learned tau={tau}")
+            for kern in ("rows", "columns"):
+                log(f"[learned] {name} tau={tau} kernel={kern}")
+                compare(b, api.align_batch(ctx, b, mode="learned", tau=tau, kernel=kern), ref,
+                        f"{name} learned tau={tau} [{kern}]")
 
 
 def test_learned_budget_saves_work_over_plain_and_constant_budgets(ctx, model_path):
-    """What the trained network gains: identical output with fewer DC lane-steps
-    than the plain method and fewer fallback attempts than constant budgets."""
+    """What the trained network gains in the row-lane kernel (where rows above
+    a window's budget are lanes not spent): identical output with fewer rows
+    computed than the plain method and fewer fallback attempts than constant
+    budgets."""
     from paper_2208_09985_amd import api
     ctx.load_model(model_path)
     b = synth.make_batch("mixed_10kbp", 300)
     runs = {}
     for name, kw in (("plain", dict(mode="plain")), ("fixed7", dict(mode="fixed", fixed_rows=7)),
                      ("fixed15", dict(mode="fixed", fixed_rows=15)), ("learned", dict(mode="learned", tau=0.9))):
-        runs[name] = api.align_batch(ctx, b, **kw)
+        runs[name] = api.align_batch(ctx, b, kernel="rows", **kw)
         st = runs[name].stats
         log(f"[gain] {name}: lane_steps={st.lane_steps} rows={st.rows_budgeted} fallback={st.fallback_windows} "
             f"rounds={st.rounds} kernel_ms={st.kernel_ms:.3f}")

@@ -23,29 +23,38 @@ def run_gpu(ctx, batch, **kw):
     return api.align_batch(ctx, batch, **kw)
 
 
-def check(ctx, batch, W=64, O=24, k=64, what="", **kw):
-    log(f"[parity] {what} pairs={batch.npairs} W={W} O={O} k={k} {kw}")
+KERNELS = ("rows", "columns")
+
+
+def check(ctx, batch, W=64, O=24, k=64, what="", kernels=KERNELS, **kw):
+    """Both fused kernels against the oracle; returns the last kernel's result."""
     ref = oracle.align_batch(batch, W, O, k)
-    gpu = run_gpu(ctx, batch, W=W, O=O, k=k, **kw)
-    compare(batch, gpu, ref, what)
+    for kern in kernels:
+        log(f"[parity] {what} pairs={batch.npairs} W={W} O={O} k={k} kernel={kern} {kw}")
+        gpu = run_gpu(ctx, batch, W=W, O=O, k=k, kernel=kern, **kw)
+        compare(batch, gpu, ref, f"{what} [{kern}]")
     return gpu, ref
 
 
 def test_small_100bp_all_pairs_plain(ctx):
     b = synth.make_batch("small_100bp")
-    gpu, ref = check(ctx, b, what="small_100bp plain")
-    assert gpu.stats.windows == ref["stats"].windows
-    assert gpu.stats.ops_alg == ref["stats"].ops_alg
+    ref = oracle.align_batch(b, 64, 24, 64)
+    for kern in KERNELS:
+        gpu, _ = check(ctx, b, what="small_100bp plain", kernels=(kern,))
+        assert gpu.stats.windows == ref["stats"].windows
+        assert gpu.stats.ops_alg == ref["stats"].ops_alg
 
 
 @pytest.mark.parametrize("mode,extra", [("fixed", dict(fixed_rows=1)), ("fixed", dict(fixed_rows=8)),
                                         ("fixed", dict(fixed_rows=16)), ("plain", dict(slots=4)),
-                                        ("fixed", dict(fixed_rows=5, slots=16))])
+                                        ("fixed", dict(fixed_rows=5, slots=16)), ("plain", dict(slots=8)),
+                                        ("fixed", dict(fixed_rows=3, slots=8))])
 def test_small_100bp_budgets_and_packing(ctx, mode, extra):
     b = synth.make_batch("small_100bp", 300)
-    gpu, ref = check(ctx, b, mode=mode, what=f"small_100bp {mode} {extra}", **extra)
-    if mode == "fixed" and extra["fixed_rows"] == 1:
-        assert gpu.stats.fallback_windows > 0
+    for kern in KERNELS:
+        gpu, ref = check(ctx, b, mode=mode, what=f"small_100bp {mode} {extra}", kernels=(kern,), **extra)
+        if mode == "fixed" and extra["fixed_rows"] == 1:
+            assert gpu.stats.fallback_windows > 0
 
 
 def test_short_250bp_subset(ctx):
@@ -126,23 +135,27 @@ def test_single_pair_api(ctx):
 def test_launch_shape_does_not_change_results(ctx):
     b = synth.make_batch("long_10kbp", indices=range(100, 132))
     ref = oracle.align_batch(b, 64, 24, 64)
-    for kw in (dict(slots=1, waves_per_cu=1), dict(slots=3, order="longest_first"), dict(slots=16, waves_per_cu=2)):
+    for kw in (dict(slots=1, waves_per_cu=1), dict(slots=3, order="longest_first"), dict(slots=16, waves_per_cu=2),
+               dict(kernel="columns", slots=4, waves_per_cu=1), dict(kernel="columns", slots=8, order="longest_first"),
+               dict(kernel="columns", slots=16, waves_per_cu=2)):
         log(f"[parity] launch shape {kw}")
+        kw.setdefault("kernel", "rows")
         compare(b, run_gpu(ctx, b, mode="fixed", fixed_rows=12, **kw), ref, f"shape {kw}")
 
 
-def test_graph_replays_match_eager(ctx):
+@pytest.mark.parametrize("kernel,mode", [("rows", "fixed"), ("columns", "plain")])
+def test_graph_replays_match_eager(ctx, kernel, mode):
     import torch
     from paper_2208_09985_amd import api
     b = synth.make_batch("short_250bp", 3000)
     ref = oracle.align_batch(b, 64, 24, 64)
-    gb = api.Batch(ctx, b, api.params(graph=True, mode="fixed", fixed_rows=8))
+    gb = api.Batch(ctx, b, api.params(graph=True, mode=mode, fixed_rows=8, kernel=kernel))
     for rep in range(4):
-        log(f"[parity] graph replay {rep}")
+        log(f"[parity] graph replay {kernel} {rep}")
         gb.edits.fill_(-7)
         gb.run()
         torch.cuda.synchronize()
-        compare(b, gb.result(), ref, f"graph replay {rep}")
+        compare(b, gb.result(), ref, f"graph replay {kernel} {rep}")
         _ = torch.ones(1000, device=gb.dev).sum().item()   # eager work between replays
     gb.close()
 
@@ -152,7 +165,7 @@ def test_long_10kbp_full_size_sampled(ctx):
     benchmark times; the oracle recomputes a random sample of pairs."""
     from paper_2208_09985_amd import api
     b = synth.make_batch("long_10kbp")
-    log("[parity] long_10kbp full size on GPU")
+    log("[parity] long_10kbp full size on GPU (the benchmark's plain launch)")
     gpu = api.align_batch(ctx, b)
     idx = np.random.default_rng(99).choice(b.npairs, 40, replace=False)
     sub = b.subset(idx)
@@ -176,10 +189,23 @@ def test_yielding_queue_keeps_results(ctx, yield_chars, kw):
     resumed on another wavefront) give the same alignments."""
     b = synth.make_batch("uneven_lognormal", indices=range(200, 260))
     ref = oracle.align_batch(b, 64, 24, 64)
-    log(f"[parity] yield_chars={yield_chars} {kw}")
-    gpu = run_gpu(ctx, b, yield_chars=yield_chars, **kw)
-    compare(b, gpu, ref, f"yield {yield_chars} {kw}")
-    if yield_chars:
-        assert gpu.stats.yields > 0
-    else:
-        assert gpu.stats.yields == 0
+    for kern in KERNELS:
+        log(f"[parity] yield_chars={yield_chars} {kw} kernel={kern}")
+        gpu = run_gpu(ctx, b, yield_chars=yield_chars, kernel=kern, **kw)
+        compare(b, gpu, ref, f"yield {yield_chars} {kw} [{kern}]")
+        if yield_chars:
+            assert gpu.stats.yields > 0
+        else:
+            assert gpu.stats.yields == 0
+
+
+def test_unrelated_pairs_long_tracebacks(ctx):
+    """Unrelated sequences: windows with distances near the pattern length and
+    tracebacks that run over several passes of the column kernel."""
+    rng = np.random.default_rng(7)
+    pats = [synth.ALPHABET[rng.integers(0, 4, int(rng.integers(50, 600)))].tobytes() for _ in range(300)]
+    txts = [synth.ALPHABET[rng.integers(0, 4, int(rng.integers(50, 600)))].tobytes() for _ in range(300)]
+    b = synth.from_lists(pats, txts)
+    for slots in (4, 8, 16):
+        check(ctx, b, what=f"unrelated slots={slots}", kernels=("columns",), slots=slots)
+    check(ctx, b, what="unrelated rows", kernels=("rows",))
