@@ -7,14 +7,16 @@ the persistent fused DC+TB kernel (every window's DC, early termination,
 traceback, CIGAR runs).  The ASCII input is resident in HBM before timing.
 Prints ONE JSON line on stdout; progress goes to stderr.
 
-Headline: plain row budget (every window may use all rows 0..k_w) on
-10,000 pairs of 10 kbp with 15% edits, W=64, O=24, k=64.  Variants on the
-same input: a constant row budget and the learned row budget, both with
-full-row fallback (all bit-identical to plain; checked here).  Two more
-workloads are reported under "workloads": 10,000 x 10 kbp pairs with a
-per-pair edit rate of 5-15% (learned vs plain), and 50,000 pairs of
-log-normal length (1-50 kbp) as one hipGraph-captured launch with the launch
-shape picked by the autotuner.
+Headline: the plain method (every window may use all rows 0..k_w) on 10,000
+pairs of 10 kbp with 15% edits, W=64, O=24, k=64, in the library's default
+kernel for it (column blocks, exact early termination per window).  Variants
+on the same input run the error-row lane kernel, where a window's row budget
+decides how many lanes it takes: plain, a constant budget and the learned
+budget, each with full-row fallback and each checked bit-identical to the
+headline's output.  Two more workloads are reported under "workloads":
+10,000 x 10 kbp pairs with a per-pair edit rate of 5-15% (learned vs plain),
+and 50,000 pairs of log-normal length (1-50 kbp) as one hipGraph-captured
+launch with the launch shape picked by the autotuner.
 
 Roofline: the kernel is bound by 32-bit bitwise VALU issue.  One 64-bit op of
 the paper's accounting is two 32-bit lane operations, so the peak is
@@ -44,8 +46,8 @@ sys.path.insert(0, ROOT)
 PEAK_T64OPS = 256 * 64 * 2.4e9 / 2 / 1e12     # 19.66 T 64-bit op/s
 METRIC = "alignments/s and Gbitops/s vs roofline, 10 kbp @15% err; learned-k vs plain"
 WEIGHTS = os.path.join(ROOT, "paper_2208_09985_amd", "weights", "budget_w64_o24.npz")
-TRAFFIC = os.path.join(ROOT, "profiles", "align_kernel_long_10kbp_traffic.txt")
-KERNEL_SOURCES = ("align.hip", "predictor.h", "internal.h")
+TRAFFIC = os.path.join(ROOT, "profiles", "cols_kernel_long_10kbp_traffic.txt")
+KERNEL_SOURCES = ("align_cols.hip", "colblock.h", "predictor.h", "internal.h")
 
 
 def log(*a):
@@ -202,13 +204,19 @@ def main():
     ms, st, res = measure(batch, "plain", api.params(W=w.W, O=w.O, k=w.k, mode="plain"), args.steps, args.warmup)
     variants = {}
     if not args.no_variants:
-        fms, fst, fres = measure(batch, "fixed", api.params(W=w.W, O=w.O, k=w.k, mode="fixed",
-                                                            fixed_rows=args.fixed_rows), args.steps, args.warmup)
-        variants[f"fixed_{args.fixed_rows}_rows"] = summary(batch, fms, fst, same_output(fres, res), ms)
+        # the row budget acts in the error-row lane kernel: plain vs fixed vs learned there
+        rms, rst, rres = measure(batch, "plain (row lanes)", api.params(W=w.W, O=w.O, k=w.k, mode="plain", kernel="rows"),
+                                 args.steps, args.warmup)
+        variants["plain_row_lanes"] = summary(batch, rms, rst, same_output(rres, res), ms)
+        fms, fst, fres = measure(batch, "fixed (row lanes)", api.params(W=w.W, O=w.O, k=w.k, mode="fixed",
+                                                                          fixed_rows=args.fixed_rows, kernel="rows"),
+                                 args.steps, args.warmup)
+        variants[f"fixed_{args.fixed_rows}_rows_row_lanes"] = summary(batch, fms, fst, same_output(fres, res), rms)
         if have_model:
-            lms, lst, lres = measure(batch, "learned", api.params(W=w.W, O=w.O, k=w.k, mode="learned"),
-                                     args.steps, args.warmup)
-            variants["learned"] = summary(batch, lms, lst, same_output(lres, res), ms)
+            lms, lst, lres = measure(batch, "learned (row lanes)", api.params(W=w.W, O=w.O, k=w.k, mode="learned",
+                                                                              kernel="rows"), args.steps, args.warmup)
+            variants["learned_row_lanes"] = summary(batch, lms, lst, same_output(lres, res), rms)
+            variants["learned_row_lanes"]["speedup_vs_headline"] = round(ms / lms, 3)
 
     workloads = {}
     if not args.no_workloads:
@@ -218,9 +226,14 @@ def main():
         ww = synth.WORKLOADS[name]
         pms, pst, pres = measure(wb, f"{name} plain", api.params(W=ww.W, O=ww.O, k=ww.k, mode="plain"), 5, 1)
         entry = {"pairs": wb.npairs, "plain": summary(wb, pms, pst)}
+        rms, rst, rres = measure(wb, f"{name} plain (row lanes)",
+                                 api.params(W=ww.W, O=ww.O, k=ww.k, mode="plain", kernel="rows"), 5, 1)
+        entry["plain_row_lanes"] = summary(wb, rms, rst, same_output(rres, pres), pms)
         if have_model:
-            lms, lst, lres = measure(wb, f"{name} learned", api.params(W=ww.W, O=ww.O, k=ww.k, mode="learned"), 5, 1)
-            entry["learned"] = summary(wb, lms, lst, same_output(lres, pres), pms)
+            lms, lst, lres = measure(wb, f"{name} learned (row lanes)",
+                                     api.params(W=ww.W, O=ww.O, k=ww.k, mode="learned", kernel="rows"), 5, 1)
+            entry["learned_row_lanes"] = summary(wb, lms, lst, same_output(lres, pres), rms)
+            entry["learned_row_lanes"]["speedup_vs_headline_kernel"] = round(pms / lms, 3)
         workloads[name] = entry
         del wb
         # uneven lengths: autotuned launch shape, one hipGraph-captured launch per step
@@ -264,8 +277,8 @@ def main():
         "gbitops_per_s": round(achieved * 1e3, 2),
         "roofline": {"bound": "alu", "achieved": round(achieved, 4), "peak": round(PEAK_T64OPS, 3),
                      "unit": "T 64-bit op/s", "frac": round(achieved / PEAK_T64OPS, 5),
-                     "traffic": measured_traffic("align_kernel_plain"),
-                     "kernel": "align_kernel<false>", "kernel_ms": round(st.kernel_ms_avg, 4),
+                     "traffic": measured_traffic("cols_kernel_plain"),
+                     "kernel": "cols_kernel<false, 8>", "kernel_ms": round(st.kernel_ms_avg, 4),
                      "ops_alg_per_launch": int(st.ops_alg), "windows_per_launch": int(st.windows)},
         "variants": variants,
         "workloads": workloads,

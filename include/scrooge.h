@@ -79,7 +79,8 @@ enum { SCG_FLAG_GRAPH = 1 };  /* replay the batch's launches from a captured hip
 enum {
     SCG_KERNEL_AUTO = 0,     /* column blocks in plain mode, error rows with a row budget     */
     SCG_KERNEL_ROWS = 1,     /* lanes are error rows; windows packed as lane segments          */
-    SCG_KERNEL_COLUMNS = 2   /* 16 windows per wavefront, 4 lanes x 16 text columns per window */
+    SCG_KERNEL_COLUMNS = 2   /* 4/8/16 windows per wavefront, lanes own text columns; a pass  */
+                             /* of row steps, then the tracebacks                              */
 };
 
 typedef struct {
@@ -92,7 +93,9 @@ typedef struct {
     float tau;              /* SCG_MODE_LEARNED: confidence needed for a smaller budget */
     int32_t flags;          /* SCG_FLAG_*                                              */
     int32_t yield_chars;    /* a pair returns to the queue after advancing this many   */
-                            /* pattern characters (0 = never; else >= W-O)             */
+                            /* pattern characters (0 = never; > 0: at least W-O;       */
+                            /* < 0: automatic, 1280 for error-row lanes, 0 for column  */
+                            /* blocks)                                                 */
     int32_t kernel;         /* SCG_KERNEL_*                                            */
 } scg_params;
 
@@ -122,8 +125,10 @@ const char* scg_strerror(int code);
 const char* scg_last_hip_error(void);
 
 /* Default parameters: W=64, O=24, k=64, plain mode, automatic launch shape
- * (slots = 1 in plain mode, 4 with a row budget; the occupancy maximum of
- * wavefronts per CU), fixed_rows = 15, tau = 0.8, yield_chars = 1280. */
+ * (column blocks with 8 windows per wavefront in plain mode, 4 with fewer
+ * than 8 pairs per CU; error-row lanes with 4 slots when windows start with
+ * a row budget; the occupancy maximum of wavefronts per CU), fixed_rows = 15,
+ * tau = 0.8, yield_chars = -1 (automatic). */
 void scg_params_default(scg_params* p);
 
 /* Create a context on HIP device `device`.  *out receives the context; the

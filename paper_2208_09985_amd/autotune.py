@@ -4,7 +4,8 @@ For a given batch and mode it times candidate configurations on the device
 (kernel time from the HIP events the library records around each launch)
 and keeps the fastest:
 
-* slots         -- windows in flight per wavefront (segments packed per round)
+* kernel        -- error-row lanes or column blocks
+* slots         -- windows in flight per wavefront
 * waves_per_cu  -- persistent wavefronts per CU (capped by LDS occupancy)
 * order         -- queue order of pairs (input order or longest first)
 * tau           -- learned mode: confidence needed before a smaller row budget
@@ -31,9 +32,11 @@ from . import api
 DEFAULT_CACHE = os.path.join(os.path.expanduser("~"), ".cache", "scrooge_mi355x", "autotune.json")
 
 SPACE = {
-    "plain": {"slots": [1, 2], "waves_per_cu": [0], "order": ["input", "longest_first"]},
-    "fixed": {"slots": [2, 4, 6, 8], "waves_per_cu": [0], "order": ["input"], "fixed_rows": [7, 11, 15, 23]},
-    "learned": {"slots": [2, 4, 6], "waves_per_cu": [0], "order": ["input"], "tau": [0.7, 0.8, 0.9]},
+    "plain": {"kernel": ["columns"], "slots": [4, 8, 16], "waves_per_cu": [0], "order": ["input", "longest_first"]},
+    "fixed": {"kernel": ["rows"], "slots": [2, 4, 6, 8], "waves_per_cu": [0], "order": ["input"],
+              "fixed_rows": [7, 11, 15, 23]},
+    "learned": {"kernel": ["rows"], "slots": [2, 4, 6], "waves_per_cu": [0], "order": ["input"],
+                "tau": [0.7, 0.8, 0.9]},
 }
 
 

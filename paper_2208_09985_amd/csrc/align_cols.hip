@@ -47,13 +47,15 @@
 //   * Pairs are taken from the global queue shared with the row-lane kernel;
 //     a pair that has advanced yield_chars pattern characters saves its
 //     state and goes back to the queue between windows.
+#include "colblock.h"
 #include "predictor.h"
 
 namespace {
 
+using namespace colblock;
+
 constexpr int kMaxGroups = 16;     // windows per wavefront, at most
 constexpr int kStoredRows = 64;    // rows 0..63 are kept for traceback
-constexpr uint32_t kDppWaveShl1 = 0x130;
 
 // A group is RUN while the pass waits for it, OVER once it has used its row
 // budget without finding d_w (it keeps computing, but the pass no longer
@@ -72,75 +74,6 @@ struct GroupRec {      // LDS: what the slot lane tells its group at set-up
     int32_t cmd;
     int32_t pad;
 };
-
-__device__ __forceinline__ uint32_t from_upper_lane(uint32_t x) {
-    // lane l receives lane l+1's value; lane 63 receives 0
-    return (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, kDppWaveShl1, 0xF, 0xF, true);
-}
-
-// Z of the initial column (i = n_w): bit j set iff m_w - j <= d
-__device__ __forceinline__ uint64_t z_init(int mw, int d) {
-    const int s = mw - d;
-    return s <= 0 ? ~0ull : (s >= 64 ? 0ull : (~0ull << s));
-}
-
-__device__ __forceinline__ int zbit(uint64_t z, int p) { return p >= 64 ? 1 : (int)((z >> p) & 1ull); }
-
-// Append `len` (>= 0) operations `op` to a pair's run list, merging equal
-// neighbours; len == 0 changes nothing.
-__device__ __forceinline__ void emit_run(int op, int len, int& cur_op, int& cur_len, int& nruns,
-                                         uint32_t* __restrict__ runs, int64_t roff, int64_t rcap) {
-    const bool same = cur_op == op;
-    const bool flush = !same && cur_len > 0 && len > 0;
-    if (flush && nruns < rcap) runs[roff + nruns] = ((uint32_t)cur_len << 2) | (uint32_t)cur_op;
-    nruns += flush ? 1 : 0;
-    cur_len = len == 0 ? cur_len : (same ? cur_len + len : len);
-    cur_op = len == 0 ? cur_op : op;
-}
-
-// One error row of the lane's CB columns: two VGPRs per column.
-template <int CB>
-struct RowRegs {
-    uint32_t lo[CB], hi[CB];
-};
-
-// Row d of columns CB*q+CB-1 .. CB*q, in place over row d-1.  (nl, nh) is row d
-// and (sl, sh) row d-1 of column CB*q+CB; tm and cin are the bits shifted in
-// by the M term and by the I/S terms.  The I, S and D terms need only row
-// d-1, so a first pass (ascending columns, each column still finds its right
-// neighbour's old value) leaves ((Z[t] | Z[t+1]) >> 1 | cin) | Z[t+1] in place;
-// the M term needs row d of the right neighbour, so a second pass runs from
-// column CB*q+CB-1 down and ORs it in.
-template <int CB>
-__device__ __forceinline__ void dc_row(RowRegs<CB>& P, const RowRegs<CB>& eq, uint32_t nl, uint32_t nh, uint32_t sl,
-                                       uint32_t sh, uint32_t tm, uint32_t cin) {
-    // first pass as register-tied assembly: each column is rewritten in its
-    // own registers (left to itself the compiler rotates the whole row
-    // through new registers and copies it back every step)
-#pragma unroll
-    for (int t = 0; t < CB; ++t) {
-        const uint32_t xl = t < CB - 1 ? P.lo[t + 1] : sl;
-        const uint32_t xh = t < CB - 1 ? P.hi[t + 1] : sh;
-        uint32_t ul, uh;
-        asm("v_or_b32 %[ul], %[pl], %[xl]\n\t"
-            "v_or_b32 %[uh], %[ph], %[xh]\n\t"
-            "v_alignbit_b32 %[pl], %[uh], %[ul], 1\n\t"
-            "v_alignbit_b32 %[ph], %[cin], %[uh], 1\n\t"
-            "v_or_b32 %[pl], %[pl], %[xl]\n\t"
-            "v_or_b32 %[ph], %[ph], %[xh]"
-            : [pl] "+v"(P.lo[t]), [ph] "+v"(P.hi[t]), [ul] "=&v"(ul), [uh] "=&v"(uh)
-            : [xl] "v"(xl), [xh] "v"(xh), [cin] "v"(cin));
-    }
-#pragma unroll
-    for (int t = CB - 1; t >= 0; --t) {
-        const uint32_t bl = __builtin_amdgcn_alignbit(nh, nl, 1);
-        const uint32_t bh = __builtin_amdgcn_alignbit(tm, nh, 1);
-        P.lo[t] = (bl & eq.lo[t]) | P.lo[t];
-        P.hi[t] = (bh & eq.hi[t]) | P.hi[t];
-        nl = P.lo[t];
-        nh = P.hi[t];
-    }
-}
 
 template <bool LEARNED, int CB>
 __global__ __launch_bounds__(64) void cols_kernel(const AlignArgs a) {
@@ -165,6 +98,7 @@ __global__ __launch_bounds__(64) void cols_kernel(const AlignArgs a) {
     bool exhausted = !slot;
     unsigned long long c_windows = 0, c_ops = 0, c_fallback = 0, c_rows = 0, c_err = 0, c_yield = 0;
     int tb_i = 0, tb_j = 0, tb_d = 0, tb_e = 0, tb_bad = 0;   // slot lane: traceback position and edits
+
     unsigned long long c_lane_steps = 0, c_rounds = 0;
 
     // ---- lane state: current row of the lane's 16 columns, their match masks ----

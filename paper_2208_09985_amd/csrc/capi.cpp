@@ -112,7 +112,7 @@ int check_params(const scg_params* p) {
     if (p->order != SCG_ORDER_INPUT && p->order != SCG_ORDER_LONGEST_FIRST) return SCG_EINVAL;
     if (p->mode == SCG_MODE_FIXED && (p->fixed_rows < 1 || p->fixed_rows > 64)) return SCG_EINVAL;
     if (p->mode == SCG_MODE_LEARNED && !(p->tau > 0.f && p->tau <= 1.f)) return SCG_EINVAL;
-    if (p->yield_chars != 0 && p->yield_chars < p->W - p->O) return SCG_EINVAL;
+    if (p->yield_chars > 0 && p->yield_chars < p->W - p->O) return SCG_EINVAL;
     if (p->kernel < SCG_KERNEL_AUTO || p->kernel > SCG_KERNEL_COLUMNS) return SCG_EINVAL;
     return SCG_OK;
 }
@@ -231,7 +231,7 @@ void scg_params_default(scg_params* p) {
     p->order = SCG_ORDER_INPUT;
     p->fixed_rows = 15;
     p->tau = 0.8f;
-    p->yield_chars = 1280;
+    p->yield_chars = -1;
 }
 
 int scg_create(scg_ctx** out, int device) {
@@ -359,6 +359,14 @@ int scg_batch_create(scg_ctx* c, const scg_params* params, int32_t npairs, const
     b->ctx = c;
     b->p = *params;
     b->npairs = npairs;
+    // automatic: column blocks for plain mode, error-row lanes when windows
+    // start with a row budget (there lanes above the budget are saved)
+    b->cols = params->kernel == SCG_KERNEL_COLUMNS ||
+              (params->kernel == SCG_KERNEL_AUTO && params->mode == SCG_MODE_PLAIN);
+    // automatic yields: the row-lane kernel hands pairs back every 1280
+    // pattern characters; the column-block kernel keeps them (its passes
+    // advance every pair by one window, so pairs finish together anyway)
+    if (b->p.yield_chars < 0) b->p.yield_chars = b->cols ? 0 : 1280;
     // host-side tables
     std::vector<int64_t> pw(npairs + 1), tw(npairs + 1);
     std::vector<int32_t> pl(npairs), tl(npairs);
@@ -376,8 +384,8 @@ int scg_batch_create(scg_ctx* c, const scg_params* params, int32_t npairs, const
     // queue capacity: the initial order plus one entry per yield; a pair
     // yields only after advancing yield_chars pattern characters
     b->qcap = npairs;
-    if (params->yield_chars > 0)
-        for (int32_t i = 0; i < npairs; ++i) b->qcap += pl[i] / params->yield_chars + 1;
+    if (b->p.yield_chars > 0)
+        for (int32_t i = 0; i < npairs; ++i) b->qcap += pl[i] / b->p.yield_chars + 1;
     std::vector<int32_t> order(npairs);
     std::iota(order.begin(), order.end(), 0);
     if (params->order == SCG_ORDER_LONGEST_FIRST)
@@ -423,17 +431,13 @@ int scg_batch_create(scg_ctx* c, const scg_params* params, int32_t npairs, const
     // host vectors die at return: wait for the copies
     if ((rc = from_hip(hipStreamSynchronize(s)))) return fail(rc);
     // launch shape
-    // automatic: column blocks for plain mode, error-row lanes when windows
-    // start with a row budget (there lanes above the budget are saved)
-    b->cols = params->kernel == SCG_KERNEL_COLUMNS ||
-              (params->kernel == SCG_KERNEL_AUTO && params->mode == SCG_MODE_PLAIN);
     const bool learned = params->mode == SCG_MODE_LEARNED;
     int per_cu;
     if (b->cols) {
         // windows per wavefront: 4, 8 or 16; automatic = enough wavefronts to
         // give every SIMD two of them
         if (params->slots > 0) b->ns = params->slots <= 4 ? 4 : (params->slots <= 8 ? 8 : 16);
-        else b->ns = npairs >= 16 * c->num_cu ? 16 : (npairs >= 8 * c->num_cu ? 8 : 4);
+        else b->ns = npairs >= 8 * c->num_cu ? 8 : 4;
         b->lds = 0;
         per_cu = cols_max_blocks_per_cu(learned, b->ns, b->lds);
     } else {

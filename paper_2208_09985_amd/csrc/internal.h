@@ -72,7 +72,7 @@ struct AlignArgs {
     int32_t* pstate;              // per pair: p0, t0, edits, nruns, cur_op, cur_len, next_w, 0
     int32_t yield_chars;          // a pair yields after advancing this many pattern chars (<= 0: never)
     unsigned long long* stats;    // ST_COUNT counters
-    // column-block kernel: stored rows of every group, [grid][16][64][dstride] u64
+    // column-block kernel: stored rows of every group, [grid][NG][64][dstride] u64
     uint64_t* dent;
     int32_t dstride;
 };

@@ -209,3 +209,27 @@ def test_unrelated_pairs_long_tracebacks(ctx):
     for slots in (4, 8, 16):
         check(ctx, b, what=f"unrelated slots={slots}", kernels=("columns",), slots=slots)
     check(ctx, b, what="unrelated rows", kernels=("rows",))
+
+
+
+def test_long_one_sided_indels(ctx):
+    """Long insertions and deletions (16-30 bases): traceback paths far from
+    the diagonal, in both kernels."""
+    rng = np.random.default_rng(11)
+    pats, txts = [], []
+    for _ in range(200):
+        p = synth.ALPHABET[rng.integers(0, 4, int(rng.integers(100, 500)))]
+        t = p.copy()
+        for _ in range(int(rng.integers(1, 4))):
+            pos = int(rng.integers(0, len(t)))
+            ln = int(rng.integers(16, 31))
+            if rng.random() < 0.5:
+                t = np.insert(t, pos, synth.ALPHABET[rng.integers(0, 4, ln)])
+            else:
+                t = np.delete(t, np.arange(pos, min(len(t), pos + ln)))
+        pats.append(p.tobytes())
+        txts.append(t.tobytes())
+    b = synth.from_lists(pats, txts)
+    check(ctx, b, what="long indels")
+    for slots in (4, 16):
+        check(ctx, b, what=f"long indels slots={slots}", kernels=("columns",), slots=slots)
