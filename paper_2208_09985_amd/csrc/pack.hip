@@ -2,10 +2,10 @@
 //
 // The paper's implementations convert each pair to a two-bit-per-base
 // encoding before alignment (Section 2.5).  Here one wavefront produces one
-// Plane2 (64 bases): lane t loads byte t of the slice (one coalesced 64-byte
-// read), and two ballots over the code bits are exactly the low and high bit
-// planes.  Lane 0 stores the 16-byte result.  The workload is a single pass
-// over the input bytes, so it is bound by HBM bandwidth.
+// Plane2 (64 bases) at a time: lane t loads byte t of the slice (one
+// coalesced 64-byte read), and two ballots over the code bits are exactly the
+// low and high bit planes.  Lane 0 stores the 16-byte result.  The workload
+// is a single pass over the input bytes, so it is bound by HBM bandwidth.
 #include "internal.h"
 
 namespace {
@@ -35,35 +35,31 @@ __device__ __forceinline__ int base_code(uint32_t c, bool& bad) {
     }
 }
 
+// One workgroup per sequence (grid-stride over sequences): wave v of the
+// block packs words v, v+4, ... of its sequence, so no word has to search for
+// the sequence it belongs to.
 __global__ __launch_bounds__(256) void pack_kernel(const uint8_t* __restrict__ seq, const int64_t* __restrict__ off,
                                                    const int64_t* __restrict__ wordoff, int32_t npairs,
-                                                   int64_t total_words, Plane2* __restrict__ out,
-                                                   uint8_t* __restrict__ bad) {
+                                                   Plane2* __restrict__ out, uint8_t* __restrict__ bad) {
     const int lane = threadIdx.x & 63;
-    const int64_t waves = (int64_t)gridDim.x * (blockDim.x >> 6);
-    int64_t w = (int64_t)blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
-    w = __builtin_amdgcn_readfirstlane((int)w);  // wave index is uniform (< 2^31 words)
-    for (; w < total_words; w += waves) {
-        // sequence s owning Plane2 w: the largest s with wordoff[s] <= w
-        int lo = 0, hi = npairs;
-        while (hi - lo > 1) {
-            const int mid = (lo + hi) >> 1;
-            if (wordoff[mid] <= w) lo = mid; else hi = mid;
+    const int wave = threadIdx.x >> 6;
+    for (int s = blockIdx.x; s < npairs; s += gridDim.x) {
+        const int64_t start = off[s];
+        const int64_t len = off[s + 1] - start;
+        const int64_t w0 = wordoff[s];
+        const int64_t nwords = wordoff[s + 1] - w0;   // (len + 63) / 64 + 1 padding word
+        bool any_bad = false;
+        for (int64_t q = wave; q < nwords; q += 4) {
+            const int64_t pos = q * 64 + lane;
+            bool badc = false;
+            int code = 0;
+            if (pos < len) code = base_code(seq[start + pos], badc);
+            const uint64_t plo = __ballot(code & 1);
+            const uint64_t phi = __ballot(code >> 1);
+            any_bad |= __ballot(badc) != 0;
+            if (lane == 0) out[w0 + q] = Plane2{plo, phi};
         }
-        const int64_t q = w - wordoff[lo];
-        const int64_t start = off[lo];
-        const int64_t len = off[lo + 1] - start;
-        const int64_t pos = q * 64 + lane;
-        bool badc = false;
-        int code = 0;
-        if (pos < len) code = base_code(seq[start + pos], badc);
-        const uint64_t plo = __ballot(code & 1);
-        const uint64_t phi = __ballot(code >> 1);
-        const uint64_t pbad = __ballot(badc);
-        if (lane == 0) {
-            out[w] = Plane2{plo, phi};
-            if (pbad) bad[lo] = 1;
-        }
+        if (lane == 0 && any_bad) bad[s] = 1;
     }
 }
 
@@ -82,10 +78,9 @@ hipError_t launch_reset(uint32_t* qctl, int32_t* ring, int64_t qcap, const int32
 hipError_t launch_pack(const uint8_t* seq, const int64_t* off, const int64_t* wordoff, int32_t npairs,
                        int64_t total_words, Plane2* out, uint8_t* bad, int num_cu, hipStream_t s) {
     if (total_words <= 0 || npairs <= 0) return hipSuccess;
-    int64_t blocks = (total_words + 3) / 4;            // 4 waves per block
-    const int64_t cap = (int64_t)num_cu * 32;           // grid-stride beyond this
+    int64_t blocks = npairs;
+    const int64_t cap = (int64_t)num_cu * 64;           // grid-stride over sequences beyond this
     if (blocks > cap) blocks = cap;
-    hipLaunchKernelGGL(pack_kernel, dim3((unsigned)blocks), dim3(256), 0, s, seq, off, wordoff, npairs,
-                       total_words, out, bad);
+    hipLaunchKernelGGL(pack_kernel, dim3((unsigned)blocks), dim3(256), 0, s, seq, off, wordoff, npairs, out, bad);
     return hipGetLastError();
 }
