@@ -83,6 +83,7 @@ __global__ __launch_bounds__(64) void cols_kernel(const AlignArgs a) {
     const int lane = threadIdx.x;
     const int g = lane / L, q = lane % L;
     const bool slot = q == 0;
+    const uint64_t gbit = 1ull << (lane - q);   // the group's slot lane in a ballot
     const int cap = a.cap;
     const int stride = a.dstride;
     uint64_t* const gdent = a.dent + ((size_t)blockIdx.x * NG + g) * (size_t)(kStoredRows * stride);
@@ -260,7 +261,7 @@ __global__ __launch_bounds__(64) void cols_kernel(const AlignArgs a) {
 
         // ---- 5. DC pass: one row of every running window per step ----
         int steps = 0;
-        while (any_run) {
+        if (any_run) do {
             // every lane computes; only lanes of running windows store and count
             const bool computing = gst == G_RUN || gst == G_OVER;
             const uint32_t tm = dl >= 0 ? 1u : 0u;    // the M term shifts in a 1 from the lane's first row on
@@ -288,22 +289,18 @@ __global__ __launch_bounds__(64) void cols_kernel(const AlignArgs a) {
             }
             // early termination: column 0 of row d has the msb of R clear
             const uint64_t hb = __ballot(slot && computing && dl >= 0 && (A.lo[0] & 1u));
-            if (computing) {
+            {   // state update without branches
                 const int d0 = dl - q;   // row of column 0 computed at this step
-                if ((hb >> (lane - q)) & 1ull) {
-                    gst = G_DONE;
-                    dw = d0;
-                } else if (d0 >= full - 1) {
-                    gst = G_DONE;        // dw = -1: no distance within rows 0..k_w
-                } else if (gst == G_RUN && d0 >= limit - 1) {
-                    gst = G_OVER;        // over budget: no longer waited for
-                    over_events += 1;
-                }
+                const bool hit = computing && (hb & gbit) != 0;
+                const bool done = hit || (computing && d0 >= full - 1);       // no hit in rows 0..k_w: dw stays -1
+                const bool over = !done && gst == G_RUN && d0 >= limit - 1;   // over budget: no longer waited for
+                dw = hit ? d0 : dw;
+                gst = done ? G_DONE : (over ? G_OVER : gst);
+                over_events += over ? 1 : 0;
             }
             dl += 1;
             steps += 1;
-            if (__ballot(gst == G_RUN) == 0) break;
-        }
+        } while (__ballot(gst == G_RUN) != 0);
         c_lane_steps += 64ull * (unsigned long long)steps;
         c_rounds += 1;
         // the group's stored rows are read by its slot lane
@@ -414,7 +411,7 @@ __global__ __launch_bounds__(64) void cols_kernel(const AlignArgs a) {
         // the group's four lanes learn that its traceback ended
         {
             const uint64_t tbm = __ballot(slot && gst == G_TB);
-            if (!((tbm >> (lane - q)) & 1ull) && gst == G_TB) gst = G_EMPTY;
+            if ((tbm & gbit) == 0 && gst == G_TB) gst = G_EMPTY;
         }
         // traceback's reads of the stored rows finish before the next pass overwrites them
         __syncthreads();

@@ -66,14 +66,18 @@ __device__ __forceinline__ void dc_row(RowRegs<CB>& P, const RowRegs<CB>& eq, ui
             : [pl] "+v"(P.lo[t]), [ph] "+v"(P.hi[t]), [ul] "=&v"(ul), [uh] "=&v"(uh)
             : [xl] "v"(xl), [xh] "v"(xh), [cin] "v"(cin));
     }
+    // second pass, also register-tied: ((right neighbour's row d) >> 1 | tm) & EQ
 #pragma unroll
     for (int t = CB - 1; t >= 0; --t) {
-        const uint32_t bl = __builtin_amdgcn_alignbit(nh, nl, 1);
-        const uint32_t bh = __builtin_amdgcn_alignbit(tm, nh, 1);
-        P.lo[t] = (bl & eq.lo[t]) | P.lo[t];
-        P.hi[t] = (bh & eq.hi[t]) | P.hi[t];
-        nl = P.lo[t];
-        nh = P.hi[t];
+        const uint32_t xl = t < CB - 1 ? P.lo[t + 1] : nl;
+        const uint32_t xh = t < CB - 1 ? P.hi[t + 1] : nh;
+        uint32_t bl, bh;
+        asm("v_alignbit_b32 %[bl], %[xh], %[xl], 1\n\t"
+            "v_alignbit_b32 %[bh], %[tm], %[xh], 1\n\t"
+            "v_and_or_b32 %[pl], %[bl], %[el], %[pl]\n\t"
+            "v_and_or_b32 %[ph], %[bh], %[eh], %[ph]"
+            : [pl] "+v"(P.lo[t]), [ph] "+v"(P.hi[t]), [bl] "=&v"(bl), [bh] "=&v"(bh)
+            : [xl] "v"(xl), [xh] "v"(xh), [tm] "v"(tm), [el] "v"(eq.lo[t]), [eh] "v"(eq.hi[t]));
     }
 }
 
