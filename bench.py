@@ -257,6 +257,29 @@ def main():
                 ref = (gms, gres)
         workloads[name] = entry
         del wb
+        # window geometry on the headline batch: throughput and windowed edit counts per (W, O);
+        # W - O <= 31 stores 32-bit entries
+        sweep = {}
+        for (W, O) in ((64, 24), (64, 33), (64, 16), (64, 40), (32, 8)):
+            sms, sst, sres = measure(batch, f"window sweep W={W} O={O}", api.params(W=W, O=O, k=W, mode="plain"), 5, 1)
+            e = summary(batch, sms, sst)
+            ach = sst.ops_alg / (sst.kernel_ms_avg / 1e3) / 1e12
+            e.update(windows=int(sst.windows), frac=round(ach / PEAK_T64OPS, 5),
+                     stored_entry_bits=32 if W - O <= 31 else 64,
+                     mean_edits=round(float(np.mean(sres.edits[sres.status == 0])), 2),
+                     aligned=int(np.sum(sres.status == 0)))
+            sweep[f"W{W}_O{O}"] = e
+        workloads["window_sweep_long_10kbp"] = sweep
+        # more pairs of the headline shape: how far latency hiding goes once the GPU holds more wavefronts
+        scale = {}
+        for n in (20000, 40000):
+            sb = synth.make_batch(args.workload, n)
+            sms, sst, _ = measure(sb, f"{args.workload} x{n}", api.params(W=w.W, O=w.O, k=w.k, mode="plain"), 5, 1)
+            e = summary(sb, sms, sst)
+            e["frac"] = round(sst.ops_alg / (sst.kernel_ms_avg / 1e3) / 1e12 / PEAK_T64OPS, 5)
+            scale[str(n)] = e
+            del sb
+        workloads["more_pairs_long_10kbp"] = scale
 
     achieved = st.ops_alg / (st.kernel_ms_avg / 1e3) / 1e12
     out = {

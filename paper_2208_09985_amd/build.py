@@ -8,6 +8,7 @@ build" check); the shared library lands next to this file.
 from __future__ import annotations
 
 import os
+import re
 import shutil
 import subprocess
 import sys
@@ -33,21 +34,54 @@ def hipcc() -> str:
     raise RuntimeError("hipcc not found")
 
 
+def register_boundary_problems(asm: str) -> list:
+    """Kernels in gfx950 assembly text where a 64-bit VALU instruction takes a
+    32-bit VGPR operand in the last register of the wavefront's allocation
+    (allocation = next_free_vgpr rounded up to 8).  A build of this kind gave
+    wrong results in wavefronts that did not start at VGPR 0 of their SIMD,
+    while the same code with a larger allocation was correct, so the build
+    refuses such code rather than ship it."""
+    problems = []
+    for m in re.finditer(r"^(_Z\w+):[^\n]*\n(.*?)s_endpgm", asm, re.S | re.M):
+        name, body = m.group(1), m.group(2)
+        d = re.search(r"\.amdhsa_kernel " + re.escape(name) + r"\n(.*?)\.end_amdhsa_kernel", asm, re.S)
+        if not d:
+            continue
+        nfv = re.search(r"\.amdhsa_next_free_vgpr (\d+)", d.group(1))
+        if not nfv:
+            continue
+        alloc = (int(nfv.group(1)) + 7) // 8 * 8
+        for line in body.splitlines():
+            code = line.split(";")[0].strip()
+            if not re.match(r"v_\w*(b64|i64|u64)\b", code) or " " not in code:
+                continue
+            for r in re.finditer(r"(?<![\[:])\bv(\d+)\b", code.split(None, 1)[1]):
+                if int(r.group(1)) + 1 >= alloc:
+                    problems.append(f"{name}: '{code}' uses v{r.group(1)}, the last of {alloc} allocated VGPRs")
+    return problems
+
+
 def build(verbose: bool = False, jobs: int = 4) -> str:
     cc = hipcc()
     tmp = tempfile.mkdtemp(prefix="scg_build_")
     try:
-        objs, procs = [], []
+        objs, procs, asms = [], [], []
         for src in SOURCES:
             obj = os.path.join(tmp, src + ".o")
             lang = ["-x", "hip"] if src.endswith(".cpp") else []
-            cmd = [cc, *HIPCC_FLAGS, *lang, "-c", os.path.join(CSRC, src), "-o", obj]
-            if verbose:
-                print(" ".join(cmd), flush=True)
-            procs.append((src, subprocess.Popen(cmd, stdout=subprocess.PIPE, stderr=subprocess.STDOUT)))
+            cmds = [[cc, *HIPCC_FLAGS, *lang, "-c", os.path.join(CSRC, src), "-o", obj]]
+            if src.endswith(".hip"):
+                # device assembly for the register-boundary check
+                asm = os.path.join(tmp, src + ".s")
+                cmds.append([cc, *HIPCC_FLAGS, "--cuda-device-only", "-S", os.path.join(CSRC, src), "-o", asm])
+                asms.append(asm)
+            for cmd in cmds:
+                if verbose:
+                    print(" ".join(cmd), flush=True)
+                procs.append((src, subprocess.Popen(cmd, stdout=subprocess.PIPE, stderr=subprocess.STDOUT)))
+                while len([p for _, p in procs if p.poll() is None]) >= jobs:
+                    next(p for _, p in procs if p.poll() is None).wait()
             objs.append(obj)
-            while len([p for _, p in procs if p.poll() is None]) >= jobs:
-                procs[0][1].wait()
         for src, p in procs:
             out, _ = p.communicate()
             text = out.decode(errors="replace")
@@ -56,6 +90,9 @@ def build(verbose: bool = False, jobs: int = 4) -> str:
                 raise RuntimeError(f"hipcc failed on {src}:\n{text}")
             if verbose and text.strip():
                 print(text)
+        problems = [q for a in asms for q in register_boundary_problems(open(a).read())]
+        if problems:
+            raise RuntimeError("register-boundary check failed:\n" + "\n".join(problems))
         tmp_lib = LIB + ".tmp"
         cmd = [cc, f"--offload-arch={ARCH}", "-shared", "-fPIC", *objs, "-o", tmp_lib]
         r = subprocess.run(cmd, stdout=subprocess.PIPE, stderr=subprocess.STDOUT)

@@ -31,7 +31,10 @@
 //   * Stored entries (Section 2.4.1, entries not edges; Section 2.4.2, only
 //     columns 0..W-O are read by traceback) go to a per-group region of
 //     global memory, [row][column] with a row stride that is a multiple of
-//     CB; each storing lane writes its CB columns with 16-byte stores.
+//     CB; each storing lane writes its CB columns with 16-byte stores.  When
+//     W-O <= 31 traceback reads bits 0..W-O only, so plain mode stores
+//     entries as their low 32 bits (NARROW; Section 2.4.2's narrower stored
+//     bitvectors).
 //   * Traceback runs in lane 0 of every finished group, all groups of the
 //     wavefront together: match runs are skipped with an XOR of the 2-bit
 //     planes and a trailing-zero count, and each edit step reads row d-1 at
@@ -75,7 +78,7 @@ struct GroupRec {      // LDS: what the slot lane tells its group at set-up
     int32_t pad;
 };
 
-template <bool LEARNED, int CB>
+template <bool LEARNED, int CB, bool NARROW>
 __global__ __launch_bounds__(64) void cols_kernel(const AlignArgs a) {
     constexpr int NG = CB;          // windows per wavefront
     constexpr int L = 64 / NG;      // lanes per window
@@ -283,9 +286,15 @@ __global__ __launch_bounds__(64) void cols_kernel(const AlignArgs a) {
             }
             // keep the row for traceback
             if (computing && storer && dl >= 0 && dl < kStoredRows) {
-                uint4* row = reinterpret_cast<uint4*>(gdent + (size_t)dl * stride + CB * q);
+                if (NARROW) {
+                    uint4* row = reinterpret_cast<uint4*>(reinterpret_cast<uint32_t*>(gdent) + (size_t)dl * stride + CB * q);
 #pragma unroll
-                for (int t = 0; t < CB; t += 2) row[t >> 1] = uint4{A.lo[t], A.hi[t], A.lo[t + 1], A.hi[t + 1]};
+                    for (int t = 0; t < CB; t += 4) row[t >> 2] = uint4{A.lo[t], A.lo[t + 1], A.lo[t + 2], A.lo[t + 3]};
+                } else {
+                    uint4* row = reinterpret_cast<uint4*>(gdent + (size_t)dl * stride + CB * q);
+#pragma unroll
+                    for (int t = 0; t < CB; t += 2) row[t >> 1] = uint4{A.lo[t], A.hi[t], A.lo[t + 1], A.hi[t + 1]};
+                }
             }
             // early termination: column 0 of row d has the msb of R clear
             const uint64_t hb = __ballot(slot && computing && dl >= 0 && (A.lo[0] & 1u));
@@ -355,9 +364,18 @@ __global__ __launch_bounds__(64) void cols_kernel(const AlignArgs a) {
                 if (!fin) {
                     // edit step: bits tj, tj+1 of row td-1 at columns ti and ti+1
                     const int ti = tb_i, tj = tb_j, td = tb_d;
-                    const uint64_t* rowp = gdent + (size_t)(max(td, 1) - 1) * stride;
-                    const uint64_t v0 = rowp[min(ti, stride - 1)];
-                    const uint64_t v1 = rowp[min(ti + 1, stride - 1)];
+                    const size_t ro = (size_t)(max(td, 1) - 1) * stride;
+                    const int c0 = min(ti, stride - 1), c1 = min(ti + 1, stride - 1);
+                    uint64_t v0, v1;
+                    if (NARROW) {
+                        const uint32_t* rowp = reinterpret_cast<const uint32_t*>(gdent) + ro;
+                        v0 = rowp[c0];
+                        v1 = rowp[c1];
+                    } else {
+                        const uint64_t* rowp = gdent + ro;
+                        v0 = rowp[c0];
+                        v1 = rowp[c1];
+                    }
                     const uint64_t rc = z_init(mw, td - 1);
                     const uint64_t za = ti < nw ? v0 : rc;        // Z[ti][td-1]
                     const uint64_t zb = ti + 1 < nw ? v1 : rc;    // Z[ti+1][td-1]
@@ -444,33 +462,43 @@ size_t cols_dent_bytes(int grid, int cap, int ng) {
     return (size_t)grid * ng * kStoredRows * (size_t)cols_dent_stride(cap, ng) * sizeof(uint64_t);
 }
 
-template <bool LEARNED>
+// 32-bit stored entries when traceback reads bits 0..31 at most; the learned
+// form keeps 64-bit entries at every W-O
+static bool cols_narrow(bool learned, int cap) { return !learned && cap <= 31; }
+
+template <bool LEARNED, bool NARROW>
 static const void* cols_fn(int ng) {
     switch (ng) {
-    case 4: return (const void*)cols_kernel<LEARNED, 4>;
-    case 8: return (const void*)cols_kernel<LEARNED, 8>;
-    default: return (const void*)cols_kernel<LEARNED, 16>;
+    case 4: return (const void*)cols_kernel<LEARNED, 4, NARROW>;
+    case 8: return (const void*)cols_kernel<LEARNED, 8, NARROW>;
+    default: return (const void*)cols_kernel<LEARNED, 16, NARROW>;
     }
 }
 
-int cols_max_blocks_per_cu(bool learned, int ng, size_t lds) {
+int cols_max_blocks_per_cu(bool learned, int ng, size_t lds, int cap) {
     int nb = 0;
-    const void* f = learned ? cols_fn<true>(ng) : cols_fn<false>(ng);
+    const void* f = learned ? cols_fn<true, false>(ng)
+                            : (cols_narrow(false, cap) ? cols_fn<false, true>(ng) : cols_fn<false, false>(ng));
     if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, f, 64, lds) != hipSuccess) return 1;
     return nb < 1 ? 1 : nb;
 }
 
 hipError_t launch_align_cols(const AlignArgs& a, int grid, int ng, size_t lds, hipStream_t s) {
     const bool learned = a.mode == 1;
-#define SCG_COLS_LAUNCH(LRN, NGV) hipLaunchKernelGGL((cols_kernel<LRN, NGV>), dim3(grid), dim3(64), lds, s, a)
+    const bool narrow = cols_narrow(learned, a.cap);
+#define SCG_COLS_LAUNCH(LRN, NGV, NRW) hipLaunchKernelGGL((cols_kernel<LRN, NGV, NRW>), dim3(grid), dim3(64), lds, s, a)
     if (learned) {
-        if (ng == 4) SCG_COLS_LAUNCH(true, 4);
-        else if (ng == 8) SCG_COLS_LAUNCH(true, 8);
-        else SCG_COLS_LAUNCH(true, 16);
+        if (ng == 4) SCG_COLS_LAUNCH(true, 4, false);
+        else if (ng == 8) SCG_COLS_LAUNCH(true, 8, false);
+        else SCG_COLS_LAUNCH(true, 16, false);
+    } else if (narrow) {
+        if (ng == 4) SCG_COLS_LAUNCH(false, 4, true);
+        else if (ng == 8) SCG_COLS_LAUNCH(false, 8, true);
+        else SCG_COLS_LAUNCH(false, 16, true);
     } else {
-        if (ng == 4) SCG_COLS_LAUNCH(false, 4);
-        else if (ng == 8) SCG_COLS_LAUNCH(false, 8);
-        else SCG_COLS_LAUNCH(false, 16);
+        if (ng == 4) SCG_COLS_LAUNCH(false, 4, false);
+        else if (ng == 8) SCG_COLS_LAUNCH(false, 8, false);
+        else SCG_COLS_LAUNCH(false, 16, false);
     }
 #undef SCG_COLS_LAUNCH
     return hipGetLastError();

@@ -439,7 +439,7 @@ int scg_batch_create(scg_ctx* c, const scg_params* params, int32_t npairs, const
         if (params->slots > 0) b->ns = params->slots <= 4 ? 4 : (params->slots <= 8 ? 8 : 16);
         else b->ns = npairs >= 8 * c->num_cu ? 8 : 4;
         b->lds = 0;
-        per_cu = cols_max_blocks_per_cu(learned, b->ns, b->lds);
+        per_cu = cols_max_blocks_per_cu(learned, b->ns, b->lds, params->W - params->O);
     } else {
         b->ns = params->slots > 0 ? params->slots : (params->mode == SCG_MODE_PLAIN ? 1 : 4);
         b->lds = align_lds_bytes(params->W - params->O + 1, b->ns);

@@ -38,6 +38,24 @@ def suffix_dp(pattern: bytes, text: bytes):
     return D
 
 
+def prefix_distance(pattern: bytes, text: bytes) -> int:
+    """min over L of levenshtein(pattern, text[0:L]) for long inputs: the
+    Wagner-Fischer rows over the text, one pattern character at a time, with
+    the in-row recurrence cur[i] = min(a[i], cur[i-1] + 1) solved as
+    i + running-min(a[k] - k) (numpy, O(m n) work, O(n) memory)."""
+    import numpy as np
+    t = np.frombuffer(text, np.uint8)
+    n = len(t)
+    idx = np.arange(n + 1, dtype=np.int64)
+    prev = idx.copy()                           # pattern prefix of length 0
+    for j, c in enumerate(pattern, start=1):
+        a = np.empty(n + 1, np.int64)
+        a[0] = j
+        a[1:] = np.minimum(prev[:-1] + (t != c), prev[1:] + 1)
+        prev = idx + np.minimum.accumulate(a - idx)
+    return int(prev.min())
+
+
 def replay(pattern: bytes, text: bytes, ops) -> tuple[int, int]:
     """Walk an op list over the two strings.  Returns (edits, text consumed).
     Raises AssertionError if an op contradicts the strings or the pattern is
