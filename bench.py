@@ -270,6 +270,16 @@ def main():
                      aligned=int(np.sum(sres.status == 0)))
             sweep[f"W{W}_O{O}"] = e
         workloads["window_sweep_long_10kbp"] = sweep
+        # lanes per window in the column-block kernel: 16, 8, 4 or 2 lanes (4, 8, 16 or 32 windows per
+        # wavefront); the error-row lane kernel's plain figure is in `variants`
+        lanes = {}
+        for ng in (4, 8, 16, 32):
+            lms_, lst_, _ = measure(batch, f"columns, {ng} windows per wavefront",
+                                    api.params(W=w.W, O=w.O, k=w.k, mode="plain", kernel="columns", slots=ng), 5, 1)
+            e = summary(batch, lms_, lst_)
+            e["lanes_per_window"] = 64 // ng
+            lanes[f"windows_per_wavefront_{ng}"] = e
+        workloads["column_blocks_long_10kbp"] = lanes
         # more pairs of the headline shape: how far latency hiding goes once the GPU holds more wavefronts
         scale = {}
         for n in (20000, 40000):

@@ -79,14 +79,16 @@ enum { SCG_FLAG_GRAPH = 1 };  /* replay the batch's launches from a captured hip
 enum {
     SCG_KERNEL_AUTO = 0,     /* column blocks in plain mode, error rows with a row budget     */
     SCG_KERNEL_ROWS = 1,     /* lanes are error rows; windows packed as lane segments          */
-    SCG_KERNEL_COLUMNS = 2   /* 4/8/16 windows per wavefront, lanes own text columns; a pass  */
-                             /* of row steps, then the tracebacks                              */
+    SCG_KERNEL_COLUMNS = 2   /* 4/8/16 windows per wavefront (32 without a learned budget),   */
+                             /* lanes own text columns; a pass of row steps, then tracebacks   */
 };
 
 typedef struct {
     int32_t W, O, k;        /* window size, overlap, edit budget per window            */
     int32_t mode;           /* SCG_MODE_*                                              */
-    int32_t slots;          /* windows in flight per wavefront, 1..16 (0 = automatic)  */
+    int32_t slots;          /* windows in flight per wavefront, 1..16 (0 = automatic); */
+                            /* column blocks round up to 4, 8, 16 or (plain and fixed  */
+                            /* modes, slots 17..32) 32                                 */
     int32_t waves_per_cu;   /* persistent wavefronts per CU (0 = occupancy maximum)    */
     int32_t order;          /* SCG_ORDER_* : queue order of pairs                      */
     int32_t fixed_rows;     /* SCG_MODE_FIXED: rows computed before falling back       */

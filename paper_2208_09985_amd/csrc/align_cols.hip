@@ -2,8 +2,9 @@
 // column-block mapping.
 //
 // Mapping (one wavefront = one workgroup, 64 lanes):
-//   * A wavefront holds NG windows of NG different pairs (NG = 4, 8 or 16),
-//     one per group of L = 64/NG consecutive lanes.  Lane q of a group owns
+//   * A wavefront holds NG windows of NG different pairs (NG = 4, 8 or 16;
+//     also 32 without a learned budget), one per group of L = 64/NG
+//     consecutive lanes.  Lane q of a group owns
 //     the CB = NG text columns CB*q .. CB*q+CB-1 of its window and keeps, for
 //     each of them, the bitvector of the current error row and the column's
 //     pattern-match mask (two VGPRs each).  Fewer windows per wavefront give
@@ -475,10 +476,17 @@ static const void* cols_fn(int ng) {
     }
 }
 
+// plain mode also has 32 windows per wavefront: two lanes per window, 32
+// columns each (the lane-per-pair end of the mapping)
+template <bool NARROW>
+static const void* cols_fn_plain(int ng) {
+    return ng == 32 ? (const void*)cols_kernel<false, 32, NARROW> : cols_fn<false, NARROW>(ng);
+}
+
 int cols_max_blocks_per_cu(bool learned, int ng, size_t lds, int cap) {
     int nb = 0;
     const void* f = learned ? cols_fn<true, false>(ng)
-                            : (cols_narrow(false, cap) ? cols_fn<false, true>(ng) : cols_fn<false, false>(ng));
+                            : (cols_narrow(false, cap) ? cols_fn_plain<true>(ng) : cols_fn_plain<false>(ng));
     if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, f, 64, lds) != hipSuccess) return 1;
     return nb < 1 ? 1 : nb;
 }
@@ -494,11 +502,13 @@ hipError_t launch_align_cols(const AlignArgs& a, int grid, int ng, size_t lds, h
     } else if (narrow) {
         if (ng == 4) SCG_COLS_LAUNCH(false, 4, true);
         else if (ng == 8) SCG_COLS_LAUNCH(false, 8, true);
-        else SCG_COLS_LAUNCH(false, 16, true);
+        else if (ng == 16) SCG_COLS_LAUNCH(false, 16, true);
+        else SCG_COLS_LAUNCH(false, 32, true);
     } else {
         if (ng == 4) SCG_COLS_LAUNCH(false, 4, false);
         else if (ng == 8) SCG_COLS_LAUNCH(false, 8, false);
-        else SCG_COLS_LAUNCH(false, 16, false);
+        else if (ng == 16) SCG_COLS_LAUNCH(false, 16, false);
+        else SCG_COLS_LAUNCH(false, 32, false);
     }
 #undef SCG_COLS_LAUNCH
     return hipGetLastError();

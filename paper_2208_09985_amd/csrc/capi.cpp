@@ -108,7 +108,10 @@ int check_params(const scg_params* p) {
     if (!p) return SCG_EINVAL;
     if (p->W < 1 || p->W > 64 || p->O < 0 || p->O >= p->W || p->k < 0 || p->k > p->W) return SCG_EINVAL;
     if (p->mode < SCG_MODE_PLAIN || p->mode > SCG_MODE_FIXED) return SCG_EINVAL;
-    if (p->slots < 0 || p->slots > kMaxSlots || p->waves_per_cu < 0) return SCG_EINVAL;
+    // column blocks without a learned budget also run 32 windows per wavefront
+    const bool cols = p->kernel == SCG_KERNEL_COLUMNS || (p->kernel == SCG_KERNEL_AUTO && p->mode == SCG_MODE_PLAIN);
+    const int max_slots = cols && p->mode != SCG_MODE_LEARNED ? 32 : kMaxSlots;
+    if (p->slots < 0 || p->slots > max_slots || p->waves_per_cu < 0) return SCG_EINVAL;
     if (p->order != SCG_ORDER_INPUT && p->order != SCG_ORDER_LONGEST_FIRST) return SCG_EINVAL;
     if (p->mode == SCG_MODE_FIXED && (p->fixed_rows < 1 || p->fixed_rows > 64)) return SCG_EINVAL;
     if (p->mode == SCG_MODE_LEARNED && !(p->tau > 0.f && p->tau <= 1.f)) return SCG_EINVAL;
@@ -436,7 +439,8 @@ int scg_batch_create(scg_ctx* c, const scg_params* params, int32_t npairs, const
     if (b->cols) {
         // windows per wavefront: 4, 8 or 16; automatic = enough wavefronts to
         // give every SIMD two of them
-        if (params->slots > 0) b->ns = params->slots <= 4 ? 4 : (params->slots <= 8 ? 8 : 16);
+        if (params->slots > 0)
+            b->ns = params->slots <= 4 ? 4 : (params->slots <= 8 ? 8 : (params->slots <= 16 ? 16 : 32));
         else b->ns = npairs >= 8 * c->num_cu ? 8 : 4;
         b->lds = 0;
         per_cu = cols_max_blocks_per_cu(learned, b->ns, b->lds, params->W - params->O);

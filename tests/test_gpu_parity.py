@@ -137,7 +137,8 @@ def test_launch_shape_does_not_change_results(ctx):
     ref = oracle.align_batch(b, 64, 24, 64)
     for kw in (dict(slots=1, waves_per_cu=1), dict(slots=3, order="longest_first"), dict(slots=16, waves_per_cu=2),
                dict(kernel="columns", slots=4, waves_per_cu=1), dict(kernel="columns", slots=8, order="longest_first"),
-               dict(kernel="columns", slots=16, waves_per_cu=2)):
+               dict(kernel="columns", slots=16, waves_per_cu=2), dict(kernel="columns", slots=32),
+               dict(kernel="columns", slots=24, waves_per_cu=1)):
         log(f"[parity] launch shape {kw}")
         kw.setdefault("kernel", "rows")
         compare(b, run_gpu(ctx, b, mode="fixed", fixed_rows=12, **kw), ref, f"shape {kw}")
