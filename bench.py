@@ -280,6 +280,17 @@ def main():
             e["lanes_per_window"] = 64 // ng
             lanes[f"windows_per_wavefront_{ng}"] = e
         workloads["column_blocks_long_10kbp"] = lanes
+        # the paper's improvements switched off one at a time in the default kernel (same alignments)
+        abl = {}
+        for tag, kw in (("all_on", {}), ("no_early_termination", dict(no_early_termination=True)),
+                        ("store_all_columns", dict(store_all_columns=True)),
+                        ("neither", dict(no_early_termination=True, store_all_columns=True))):
+            ams, ast, ares = measure(batch, f"ablation {tag}",
+                                     api.params(W=w.W, O=w.O, k=w.k, mode="plain", kernel="columns", **kw), 5, 1)
+            e = summary(batch, ams, ast, same_output(ares, res))
+            e["rows_computed"] = int(ast.rows_budgeted)
+            abl[tag] = e
+        workloads["ablation_long_10kbp"] = abl
         # more pairs of the headline shape: how far latency hiding goes once the GPU holds more wavefronts
         scale = {}
         for n in (20000, 40000):

@@ -73,7 +73,14 @@ enum {
 
 enum { SCG_ORDER_INPUT = 0, SCG_ORDER_LONGEST_FIRST = 1 };
 enum { SCG_WHERE_HOST = 0, SCG_WHERE_DEVICE = 1 };
-enum { SCG_FLAG_GRAPH = 1 };  /* replay the batch's launches from a captured hipGraph */
+enum {
+    SCG_FLAG_GRAPH = 1,              /* replay the batch's launches from a captured hipGraph   */
+    /* Ablations of the paper's improvements (Section 2.4), plain mode in the column-block     */
+    /* kernel only (SCG_EINVAL otherwise); results are unchanged, only the work grows:         */
+    SCG_FLAG_NO_EARLY_TERMINATION = 2,  /* every window computes all k_w+1 rows (no ET)        */
+    SCG_FLAG_STORE_ALL_COLUMNS = 4      /* store every column of a row, not only 0..W-O (no    */
+                                        /* DENT)                                               */
+};
 
 /* which fused kernel aligns the batch (same results, different mappings) */
 enum {

@@ -17,6 +17,8 @@ MODE_PLAIN, MODE_LEARNED, MODE_FIXED = 0, 1, 2
 ORDER_INPUT, ORDER_LONGEST_FIRST = 0, 1
 WHERE_HOST, WHERE_DEVICE = 0, 1
 FLAG_GRAPH = 1
+FLAG_NO_EARLY_TERMINATION = 2
+FLAG_STORE_ALL_COLUMNS = 4
 KERNEL_AUTO, KERNEL_ROWS, KERNEL_COLUMNS = 0, 1, 2
 NFEATURES = 16
 

@@ -33,7 +33,8 @@ def _stream_ptr(stream) -> ctypes.c_void_p:
 
 
 def params(W=64, O=24, k=64, mode="plain", slots=0, waves_per_cu=0, order="input", fixed_rows=None, tau=None,
-           graph=False, yield_chars=None, kernel="auto") -> L.Params:
+           graph=False, yield_chars=None, kernel="auto", no_early_termination=False,
+           store_all_columns=False) -> L.Params:
     p = L.Params()
     L.load().scg_params_default(ctypes.byref(p))
     p.W, p.O, p.k = W, O, k
@@ -44,7 +45,8 @@ def params(W=64, O=24, k=64, mode="plain", slots=0, waves_per_cu=0, order="input
         p.fixed_rows = fixed_rows
     if tau is not None:
         p.tau = tau
-    p.flags = L.FLAG_GRAPH if graph else 0
+    p.flags = ((L.FLAG_GRAPH if graph else 0) | (L.FLAG_NO_EARLY_TERMINATION if no_early_termination else 0)
+               | (L.FLAG_STORE_ALL_COLUMNS if store_all_columns else 0))
     if yield_chars is not None:
         p.yield_chars = yield_chars
     p.kernel = {"auto": L.KERNEL_AUTO, "rows": L.KERNEL_ROWS, "columns": L.KERNEL_COLUMNS}[kernel]

@@ -301,8 +301,8 @@ __global__ __launch_bounds__(64) void cols_kernel(const AlignArgs a) {
             const uint64_t hb = __ballot(slot && computing && dl >= 0 && (A.lo[0] & 1u));
             {   // state update without branches
                 const int d0 = dl - q;   // row of column 0 computed at this step
-                const bool hit = computing && (hb & gbit) != 0;
-                const bool done = hit || (computing && d0 >= full - 1);       // no hit in rows 0..k_w: dw stays -1
+                const bool hit = computing && (hb & gbit) != 0 && dw < 0;   // first row with a hit
+                const bool done = (hit && !a.no_et) || (computing && d0 >= full - 1);   // no hit: dw stays -1
                 const bool over = !done && gst == G_RUN && d0 >= limit - 1;   // over budget: no longer waited for
                 dw = hit ? d0 : dw;
                 gst = done ? G_DONE : (over ? G_OVER : gst);
@@ -324,7 +324,7 @@ __global__ __launch_bounds__(64) void cols_kernel(const AlignArgs a) {
         // this round and continues in the next one, so one long path does
         // not hold the whole wavefront.
         if (slot && gst == G_DONE) {
-            c_rows += (unsigned long long)(dw < 0 ? full : dw + 1);
+            c_rows += (unsigned long long)(dw < 0 || a.no_et ? full : dw + 1);
             tb_d = dw;
             if (tb_d < 0 && kw == mw) tb_d = mw;   // no hit in rows 0..m_w-1: distance m_w
             if (tb_d < 0) {

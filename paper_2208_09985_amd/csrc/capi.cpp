@@ -117,6 +117,10 @@ int check_params(const scg_params* p) {
     if (p->mode == SCG_MODE_LEARNED && !(p->tau > 0.f && p->tau <= 1.f)) return SCG_EINVAL;
     if (p->yield_chars > 0 && p->yield_chars < p->W - p->O) return SCG_EINVAL;
     if (p->kernel < SCG_KERNEL_AUTO || p->kernel > SCG_KERNEL_COLUMNS) return SCG_EINVAL;
+    if (p->flags & ~(SCG_FLAG_GRAPH | SCG_FLAG_NO_EARLY_TERMINATION | SCG_FLAG_STORE_ALL_COLUMNS)) return SCG_EINVAL;
+    if ((p->flags & (SCG_FLAG_NO_EARLY_TERMINATION | SCG_FLAG_STORE_ALL_COLUMNS)) &&
+        (p->mode != SCG_MODE_PLAIN || p->kernel == SCG_KERNEL_ROWS))
+        return SCG_EINVAL;
     return SCG_OK;
 }
 
@@ -192,6 +196,7 @@ int enqueue_run(scg_batch* b, hipStream_t s, int32_t* edits, int32_t* text_end, 
     a.stats = b->stats_d;
     a.dent = b->dent_d;
     a.dstride = b->dstride;
+    a.no_et = (b->p.flags & SCG_FLAG_NO_EARLY_TERMINATION) ? 1 : 0;
     if (b->npairs > 0) {
         if (b->cols) HIP_TRY(launch_align_cols(a, b->grid, b->ns, b->lds, s));
         else HIP_TRY(launch_align(a, b->grid, b->lds, s));
@@ -455,8 +460,10 @@ int scg_batch_create(scg_ctx* c, const scg_params* params, int32_t npairs, const
     if (b->grid > need) b->grid = (int)std::max<int64_t>(1, need);
     if (b->cols && npairs > 0) {
         const int cap = params->W - params->O;
-        b->dstride = cols_dent_stride(cap, b->ns);
-        if ((rc = dev_alloc(&b->dent_d, cols_dent_bytes(b->grid, cap, b->ns) / sizeof(uint64_t)))) return fail(rc);
+        // stored columns 0..cap (DENT), or all of them for the ablation
+        const int scap = (params->flags & SCG_FLAG_STORE_ALL_COLUMNS) ? 63 : cap;
+        b->dstride = cols_dent_stride(scap, b->ns);
+        if ((rc = dev_alloc(&b->dent_d, cols_dent_bytes(b->grid, scap, b->ns) / sizeof(uint64_t)))) return fail(rc);
     }
     *out = b;
     return SCG_OK;

@@ -75,6 +75,7 @@ struct AlignArgs {
     // column-block kernel: stored rows of every group, [grid][NG][64][dstride] u64
     uint64_t* dent;
     int32_t dstride;
+    int32_t no_et;                // ablation: rows continue past d_w up to k_w
 };
 
 // launchers (defined in the .hip files)

@@ -144,6 +144,17 @@ def test_launch_shape_does_not_change_results(ctx):
         compare(b, run_gpu(ctx, b, mode="fixed", fixed_rows=12, **kw), ref, f"shape {kw}")
 
 
+@pytest.mark.parametrize("W,O", [(64, 24), (64, 40)])
+def test_ablation_flags_keep_results(ctx, W, O):
+    # no early termination / all columns stored: more work, same alignments
+    b = synth.make_batch("long_10kbp", indices=range(200, 232))
+    ref = oracle.align_batch(b, W, O, W)
+    for kw in (dict(no_early_termination=True), dict(store_all_columns=True),
+               dict(no_early_termination=True, store_all_columns=True, slots=4)):
+        log(f"[parity] ablation W={W} O={O} {kw}")
+        compare(b, run_gpu(ctx, b, W=W, O=O, k=W, kernel="columns", **kw), ref, f"ablation {kw}")
+
+
 @pytest.mark.parametrize("kernel,mode", [("rows", "fixed"), ("columns", "plain")])
 def test_graph_replays_match_eager(ctx, kernel, mode):
     import torch
