@@ -49,22 +49,35 @@ struct RowRegs {
 template <int CB>
 __device__ __forceinline__ void dc_row(RowRegs<CB>& P, const RowRegs<CB>& eq, uint32_t nl, uint32_t nh, uint32_t sl,
                                        uint32_t sh, uint32_t tm, uint32_t cin) {
-    // first pass as register-tied assembly: each column is rewritten in its
-    // own registers (left to itself the compiler rotates the whole row
-    // through new registers and copies it back every step)
+    // first pass as register-tied assembly, in three sweeps over the columns
+    // so that no instruction waits on the one just before it: U = Z[t] |
+    // Z[t+1]; U = U >> 1 | cin; Z[t] = U | Z[t+1] (ascending, so Z[t+1] is
+    // still row d-1).  Left to itself the compiler rotates the whole row
+    // through new registers and copies it back every step.
+    uint32_t ul[CB], uh[CB];
 #pragma unroll
     for (int t = 0; t < CB; ++t) {
         const uint32_t xl = t < CB - 1 ? P.lo[t + 1] : sl;
         const uint32_t xh = t < CB - 1 ? P.hi[t + 1] : sh;
-        uint32_t ul, uh;
-        asm("v_or_b32 %[ul], %[pl], %[xl]\n\t"
-            "v_or_b32 %[uh], %[ph], %[xh]\n\t"
-            "v_alignbit_b32 %[pl], %[uh], %[ul], 1\n\t"
-            "v_alignbit_b32 %[ph], %[cin], %[uh], 1\n\t"
-            "v_or_b32 %[pl], %[pl], %[xl]\n\t"
-            "v_or_b32 %[ph], %[ph], %[xh]"
-            : [pl] "+v"(P.lo[t]), [ph] "+v"(P.hi[t]), [ul] "=&v"(ul), [uh] "=&v"(uh)
-            : [xl] "v"(xl), [xh] "v"(xh), [cin] "v"(cin));
+        asm volatile("v_or_b32 %[ul], %[pl], %[xl]\n\t"
+                     "v_or_b32 %[uh], %[ph], %[xh]"
+                     : [ul] "=&v"(ul[t]), [uh] "=&v"(uh[t])
+                     : [pl] "v"(P.lo[t]), [ph] "v"(P.hi[t]), [xl] "v"(xl), [xh] "v"(xh));
+    }
+#pragma unroll
+    for (int t = 0; t < CB; ++t)
+        asm volatile("v_alignbit_b32 %[ul], %[uh], %[ul], 1\n\t"
+                     "v_alignbit_b32 %[uh], %[cin], %[uh], 1"
+                     : [ul] "+v"(ul[t]), [uh] "+v"(uh[t])
+                     : [cin] "v"(cin));
+#pragma unroll
+    for (int t = 0; t < CB; ++t) {
+        const uint32_t xl = t < CB - 1 ? P.lo[t + 1] : sl;
+        const uint32_t xh = t < CB - 1 ? P.hi[t + 1] : sh;
+        asm volatile("v_or_b32 %[pl], %[ul], %[xl]\n\t"
+                     "v_or_b32 %[ph], %[uh], %[xh]"
+                     : [pl] "+v"(P.lo[t]), [ph] "+v"(P.hi[t])
+                     : [ul] "v"(ul[t]), [uh] "v"(uh[t]), [xl] "v"(xl), [xh] "v"(xh));
     }
     // second pass, also register-tied: ((right neighbour's row d) >> 1 | tm) & EQ
 #pragma unroll
@@ -72,12 +85,14 @@ __device__ __forceinline__ void dc_row(RowRegs<CB>& P, const RowRegs<CB>& eq, ui
         const uint32_t xl = t < CB - 1 ? P.lo[t + 1] : nl;
         const uint32_t xh = t < CB - 1 ? P.hi[t + 1] : nh;
         uint32_t bl, bh;
-        asm("v_alignbit_b32 %[bl], %[xh], %[xl], 1\n\t"
-            "v_alignbit_b32 %[bh], %[tm], %[xh], 1\n\t"
-            "v_and_or_b32 %[pl], %[bl], %[el], %[pl]\n\t"
-            "v_and_or_b32 %[ph], %[bh], %[eh], %[ph]"
-            : [pl] "+v"(P.lo[t]), [ph] "+v"(P.hi[t]), [bl] "=&v"(bl), [bh] "=&v"(bh)
-            : [xl] "v"(xl), [xh] "v"(xh), [tm] "v"(tm), [el] "v"(eq.lo[t]), [eh] "v"(eq.hi[t]));
+        // high half first: the next column's first instruction then reads
+        // a result two instructions old
+        asm volatile("v_alignbit_b32 %[bh], %[tm], %[xh], 1\n\t"
+                     "v_alignbit_b32 %[bl], %[xh], %[xl], 1\n\t"
+                     "v_and_or_b32 %[ph], %[bh], %[eh], %[ph]\n\t"
+                     "v_and_or_b32 %[pl], %[bl], %[el], %[pl]"
+                     : [pl] "+v"(P.lo[t]), [ph] "+v"(P.hi[t]), [bl] "=&v"(bl), [bh] "=&v"(bh)
+                     : [xl] "v"(xl), [xh] "v"(xh), [tm] "v"(tm), [el] "v"(eq.lo[t]), [eh] "v"(eq.hi[t]));
     }
 }
 
