@@ -1,11 +1,12 @@
 // Encode + pack: ASCII sequences to the planar 2-bit layout (Plane2).
 //
 // The paper's implementations convert each pair to a two-bit-per-base
-// encoding before alignment (Section 2.5).  Here one wavefront produces one
-// Plane2 (64 bases) at a time: lane t loads byte t of the slice (one
-// coalesced 64-byte read), and two ballots over the code bits are exactly the
-// low and high bit planes.  Lane 0 stores the 16-byte result.  The workload
-// is a single pass over the input bytes, so it is bound by HBM bandwidth.
+// encoding before alignment (Section 2.5).  Here a wavefront produces eight
+// Plane2 (64 bases each) per iteration: for each, lane t loads byte t of the
+// slice (a coalesced 64-byte read; all eight loads are issued before the
+// first is used), and two ballots over the code bits are exactly the low and
+// high bit planes.  Lane 0 stores the 16-byte results.  The workload is a
+// single pass over the input bytes, so it is bound by HBM bandwidth.
 #include "internal.h"
 
 namespace {
@@ -36,8 +37,8 @@ __device__ __forceinline__ int base_code(uint32_t c, bool& bad) {
 }
 
 // One workgroup per sequence (grid-stride over sequences): wave v of the
-// block packs words v, v+4, ... of its sequence, so no word has to search for
-// the sequence it belongs to.
+// block packs words 8v..8v+7, 8v+32..8v+39, ... of its sequence, so no word
+// has to search for the sequence it belongs to.
 __global__ __launch_bounds__(256) void pack_kernel(const uint8_t* __restrict__ seq, const int64_t* __restrict__ off,
                                                    const int64_t* __restrict__ wordoff, int32_t npairs,
                                                    Plane2* __restrict__ out, uint8_t* __restrict__ bad) {
@@ -49,15 +50,27 @@ __global__ __launch_bounds__(256) void pack_kernel(const uint8_t* __restrict__ s
         const int64_t w0 = wordoff[s];
         const int64_t nwords = wordoff[s + 1] - w0;   // (len + 63) / 64 + 1 padding word
         bool any_bad = false;
-        for (int64_t q = wave; q < nwords; q += 4) {
-            const int64_t pos = q * 64 + lane;
-            bool badc = false;
-            int code = 0;
-            if (pos < len) code = base_code(seq[start + pos], badc);
-            const uint64_t plo = __ballot(code & 1);
-            const uint64_t phi = __ballot(code >> 1);
-            any_bad |= __ballot(badc) != 0;
-            if (lane == 0) out[w0 + q] = Plane2{plo, phi};
+        // kWords words per wavefront per iteration: their byte loads are all
+        // in flight before the first ballot needs one
+        constexpr int kWords = 8;
+        for (int64_t q0 = (int64_t)wave * kWords; q0 < nwords; q0 += 4 * kWords) {
+            uint32_t c[kWords];
+#pragma unroll
+            for (int u = 0; u < kWords; ++u) {
+                const int64_t pos = (q0 + u) * 64 + lane;
+                c[u] = pos < len ? seq[start + pos] : 'a';   // past the end: a valid placeholder, masked below
+            }
+#pragma unroll
+            for (int u = 0; u < kWords; ++u) {
+                const int64_t q = q0 + u;
+                const int64_t pos = q * 64 + lane;
+                bool badc = false;
+                const int code = pos < len ? base_code(c[u], badc) : 0;
+                const uint64_t plo = __ballot(code & 1);
+                const uint64_t phi = __ballot(code >> 1);
+                any_bad |= __ballot(badc) != 0;
+                if (lane == 0 && q < nwords) out[w0 + q] = Plane2{plo, phi};
+            }
         }
         if (lane == 0 && any_bad) bad[s] = 1;
     }
