@@ -199,6 +199,26 @@ int scg_align(scg_ctx* ctx, const char* pattern, int32_t m, const char* text, in
               int32_t W, int32_t O, int32_t k, int32_t* edits, int32_t* text_end,
               char* cigar, int32_t cigar_cap, int32_t* cigar_len);
 
+/* A whole batch in one call (the align-all call of supplementary Section 7,
+ * tool function calls): scg_batch_create + scg_batch_run + synchronise +
+ * destroy.
+ * Inputs as in scg_batch_create.  Outputs live where the inputs do: with
+ * SCG_WHERE_HOST they are host arrays (the library allocates device
+ * buffers for the run and copies back), with SCG_WHERE_DEVICE device arrays
+ * written in place.  edits, text_end, status, n_runs: npairs int32 each;
+ * runs: sum over pairs of (m + n + 1) uint32 words, pair p starting at
+ * sum over i < p of (m_i + n_i + 1).  Returns when the outputs are complete.
+ * The counters and timings of the run are kept for scg_last_stats.
+ * Errors: as scg_batch_create and scg_batch_run. */
+int scg_align_batch(scg_ctx* ctx, const scg_params* params, int32_t npairs,
+                    const void* pat, const int64_t* pat_off, const void* txt, const int64_t* txt_off,
+                    int32_t where, void* stream, int32_t* edits, int32_t* text_end, int32_t* status,
+                    uint32_t* runs, int32_t* n_runs);
+
+/* Counters and timings of the context's last scg_align_batch (zeros before
+ * the first).  Errors: SCG_EINVAL. */
+int scg_last_stats(const scg_ctx* ctx, scg_stats* out);
+
 /* Render run words as a CIGAR string (host memory). */
 int scg_runs_to_cigar(const uint32_t* runs, int32_t n_runs, char* cigar, int32_t cap, int32_t* len);
 

@@ -25,7 +25,8 @@ NFEATURES = 16
 EXPORTED = [
     "scg_strerror", "scg_last_hip_error", "scg_params_default", "scg_create", "scg_destroy", "scg_device_cus", "scg_set_model",
     "scg_batch_create", "scg_batch_destroy", "scg_batch_runs_capacity", "scg_batch_runs_offsets",
-    "scg_batch_run", "scg_batch_stats", "scg_align", "scg_runs_to_cigar", "scg_features",
+    "scg_batch_run", "scg_batch_stats", "scg_align", "scg_align_batch", "scg_last_stats", "scg_runs_to_cigar",
+    "scg_features",
     "scg_mlp_forward", "scg_mlp_backward", "scg_adam_step",
 ]
 
@@ -85,6 +86,8 @@ def load():
         "scg_batch_runs_offsets": ([P, P], ctypes.c_int),
         "scg_batch_run": ([P, P, P, P, P, P, P], ctypes.c_int),
         "scg_batch_stats": ([P, ctypes.POINTER(Stats)], ctypes.c_int),
+        "scg_align_batch": ([P, ctypes.POINTER(Params), i32, P, P, P, P, i32, P, P, P, P, P, P], ctypes.c_int),
+        "scg_last_stats": ([P, ctypes.POINTER(Stats)], ctypes.c_int),
         "scg_align": ([P, ctypes.c_char_p, i32, ctypes.c_char_p, i32, i32, i32, i32, P, P, ctypes.c_char_p, i32, P],
                       ctypes.c_int),
         "scg_runs_to_cigar": ([P, i32, ctypes.c_char_p, i32, P], ctypes.c_int),

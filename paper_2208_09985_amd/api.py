@@ -216,3 +216,41 @@ def align_batch(ctx: Context, batch, W=64, O=24, k=64, mode="plain", **kw) -> Re
     b.close()
     res.stats = st
     return res
+
+
+def align_batch_once(ctx: Context, batch, W=64, O=24, k=64, mode="plain", host=True, **kw) -> Result:
+    """One scg_align_batch call: host arrays in and out (host=True), or device
+    tensors in and out (host=False).  Returns host results with .stats."""
+    import torch
+    prm = params(W=W, O=O, k=k, mode=mode, **kw)
+    n = int(len(batch.pat_off) - 1)
+    pat_off = np.ascontiguousarray(batch.pat_off, dtype=np.int64)
+    txt_off = np.ascontiguousarray(batch.txt_off, dtype=np.int64)
+    lens = (pat_off[1:] - pat_off[:-1]) + (txt_off[1:] - txt_off[:-1]) + 1
+    runs_off = np.zeros(n + 1, np.int64)
+    np.cumsum(lens, out=runs_off[1:])
+    cap = max(int(runs_off[-1]), 1)
+    lib = ctx._lib
+    if host:
+        pat, txt = np.ascontiguousarray(batch.pat), np.ascontiguousarray(batch.txt)
+        outs = [np.zeros(max(n, 1), np.int32) for _ in range(4)]
+        runs = np.zeros(cap, np.uint32)
+        where, stream = L.WHERE_HOST, None
+    else:
+        dev = torch.device(f"cuda:{ctx.device}")
+        pat = torch.from_numpy(np.ascontiguousarray(batch.pat)).to(dev)
+        txt = torch.from_numpy(np.ascontiguousarray(batch.txt)).to(dev)
+        outs = [torch.zeros(max(n, 1), dtype=torch.int32, device=dev) for _ in range(4)]
+        runs = torch.zeros(cap, dtype=torch.int32, device=dev)
+        torch.cuda.synchronize(dev)
+        where, stream = L.WHERE_DEVICE, None
+    rc = lib.scg_align_batch(ctx.handle, ctypes.byref(prm), n, _ptr(pat), _ptr(pat_off), _ptr(txt), _ptr(txt_off),
+                             where, _stream_ptr(stream), _ptr(outs[0]), _ptr(outs[1]), _ptr(outs[2]), _ptr(runs),
+                             _ptr(outs[3]))
+    L.check(rc, "scg_align_batch")
+    st = L.Stats()
+    L.check(lib.scg_last_stats(ctx.handle, ctypes.byref(st)), "scg_last_stats")
+    res = Result(outs[0][:n], outs[1][:n], outs[2][:n], runs, outs[3][:n], runs_off).to_host()
+    res.runs = np.asarray(res.runs).view(np.uint32)
+    res.stats = st
+    return res

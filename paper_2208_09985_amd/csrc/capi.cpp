@@ -25,6 +25,7 @@ struct scg_ctx {
     __half* model_d = nullptr;      // w1 | b1 | w2 | b2
     int32_t* budget_d = nullptr;
     uint32_t* operands_d = nullptr; // per-lane MFMA operand blob (64 lanes x 144 B)
+    scg_stats last{};               // stats of the last scg_align_batch
 };
 
 struct scg_batch {
@@ -619,6 +620,51 @@ int scg_align(scg_ctx* c, const char* pattern, int32_t m, const char* text, int3
     *text_end = h[1];
     if (h[2] == SCG_PAIR_ERROR) return SCG_EINTERNAL;
     return scg_runs_to_cigar(runs.data(), (int32_t)runs.size(), cigar, cigar_cap, cigar_len);
+}
+
+int scg_align_batch(scg_ctx* c, const scg_params* params, int32_t npairs, const void* pat, const int64_t* pat_off,
+                    const void* txt, const int64_t* txt_off, int32_t where, void* stream, int32_t* edits,
+                    int32_t* text_end, int32_t* status, uint32_t* runs, int32_t* n_runs) {
+    if (!c || npairs < 0 || (npairs > 0 && (!edits || !text_end || !status || !runs || !n_runs))) return SCG_EINVAL;
+    scg_batch* b = nullptr;
+    int rc = scg_batch_create(c, params, npairs, pat, pat_off, txt, txt_off, where, stream, &b);
+    if (rc) return rc;
+    hipStream_t s = (hipStream_t)stream;
+    if (where == SCG_WHERE_DEVICE) {
+        rc = scg_batch_run(b, stream, edits, text_end, status, runs, n_runs);
+    } else {
+        // host outputs: run into device buffers, then copy back
+        const int64_t cap = scg_batch_runs_capacity(b);
+        int32_t* outs = nullptr;
+        uint32_t* runs_d = nullptr;
+        rc = dev_alloc(&outs, 4 * (size_t)npairs);
+        if (!rc) rc = dev_alloc(&runs_d, (size_t)cap);
+        if (!rc) rc = scg_batch_run(b, stream, outs, outs + npairs, outs + 2 * (size_t)npairs, runs_d,
+                                    outs + 3 * (size_t)npairs);
+        const size_t n4 = sizeof(int32_t) * (size_t)npairs;
+        if (!rc && npairs > 0) {
+            rc = from_hip(hipMemcpyAsync(edits, outs, n4, hipMemcpyDeviceToHost, s));
+            if (!rc) rc = from_hip(hipMemcpyAsync(text_end, outs + npairs, n4, hipMemcpyDeviceToHost, s));
+            if (!rc) rc = from_hip(hipMemcpyAsync(status, outs + 2 * (size_t)npairs, n4, hipMemcpyDeviceToHost, s));
+            if (!rc) rc = from_hip(hipMemcpyAsync(n_runs, outs + 3 * (size_t)npairs, n4, hipMemcpyDeviceToHost, s));
+            if (!rc) rc = from_hip(hipMemcpyAsync(runs, runs_d, sizeof(uint32_t) * (size_t)cap, hipMemcpyDeviceToHost, s));
+        }
+        if (!rc) rc = from_hip(hipStreamSynchronize(s));
+        if (outs) (void)hipFree(outs);
+        if (runs_d) (void)hipFree(runs_d);
+    }
+    scg_stats st{};
+    const int src = rc ? rc : scg_batch_stats(b, &st);   // also waits for a device-output run
+    scg_batch_destroy(b);
+    if (src && src != SCG_EINTERNAL) return src;
+    c->last = st;
+    return src;
+}
+
+int scg_last_stats(const scg_ctx* c, scg_stats* out) {
+    if (!c || !out) return SCG_EINVAL;
+    *out = c->last;
+    return SCG_OK;
 }
 
 int scg_features(scg_batch* b, int32_t nwin, const int32_t* windows, uint16_t* features, void* stream) {

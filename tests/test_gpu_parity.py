@@ -245,3 +245,15 @@ def test_long_one_sided_indels(ctx):
     check(ctx, b, what="long indels")
     for slots in (4, 16):
         check(ctx, b, what=f"long indels slots={slots}", kernels=("columns",), slots=slots)
+
+
+def test_one_shot_batch_call(ctx):
+    # scg_align_batch: host arrays in and out, and device arrays in and out
+    from paper_2208_09985_amd import api
+    b = synth.make_batch("uneven_lognormal", 24)
+    ref = oracle.align_batch(b, 64, 24, 64)
+    for host in (True, False):
+        log(f"[parity] one-shot batch call host={host}")
+        res = api.align_batch_once(ctx, b, host=host)
+        compare(b, res, ref, f"one-shot host={host}")
+        assert res.stats.windows > 0 and res.stats.kernel_ms > 0
