@@ -17,6 +17,7 @@ import numpy as np
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 SRC = os.path.join(HERE, "scrooge_oracle.c")
+INC = os.path.join(HERE, "oracle_width.inc")   # width-generic body, included twice by SRC
 BUILD_DIR = os.path.join(HERE, "_build")
 LIB_PATH = os.path.join(BUILD_DIR, "liboracle.so")
 
@@ -60,13 +61,16 @@ _lib = None
 def lib():
     global _lib
     if _lib is None:
-        if not os.path.exists(LIB_PATH) or os.path.getmtime(LIB_PATH) < os.path.getmtime(SRC):
+        if not os.path.exists(LIB_PATH) or os.path.getmtime(LIB_PATH) < max(os.path.getmtime(SRC),
+                                                                              os.path.getmtime(INC)):
             build()
         L = ctypes.CDLL(LIB_PATH)
         P = ctypes.c_void_p
         i32, i64 = ctypes.c_int32, ctypes.c_int64
         L.or_dc_table.argtypes = [P, i32, P, i32, i32, P, P]
         L.or_dc_table.restype = ctypes.c_int
+        L.or_dc_table_wide.argtypes = [P, i32, P, i32, i32, P, P]
+        L.or_dc_table_wide.restype = ctypes.c_int
         L.or_pattern_masks.argtypes = [P, i32, P]
         L.or_pattern_masks.restype = ctypes.c_int
         L.or_align_pair.argtypes = [P, i32, P, i32, i32, i32, i32, P, P, P, i64, P, P, P, i64, P, i32]
@@ -93,6 +97,24 @@ def dc_table(pattern: bytes, text: bytes, k: int):
     rc = lib().or_dc_table(_ptr(p), m, _ptr(t), n, k, _ptr(R), ctypes.byref(dw))
     if rc != 0:
         raise ValueError(f"or_dc_table rc={rc}")
+    return R, dw.value
+
+
+def dc_table_wide(pattern: bytes, text: bytes, k: int):
+    """Algorithm 1 on one window of up to 128 characters (the 128-bit
+    instantiation).  Returns (R, d): R[i, d] as Python ints in the paper's bit
+    order (bit j of the pattern at bit m-1-j), d as in dc_table."""
+    m, n = len(pattern), len(text)
+    R2 = np.zeros((n + 1) * (k + 1) * 2, dtype=np.uint64)
+    dw = ctypes.c_int32(0)
+    p = np.frombuffer(pattern, np.uint8).copy()
+    t = np.frombuffer(text, np.uint8).copy() if n else np.zeros(1, np.uint8)
+    rc = lib().or_dc_table_wide(_ptr(p), m, _ptr(t), n, k, _ptr(R2), ctypes.byref(dw))
+    if rc != 0:
+        raise ValueError(f"or_dc_table_wide rc={rc}")
+    R = np.empty((n + 1, k + 1), dtype=object)
+    for x in range((n + 1) * (k + 1)):
+        R.flat[x] = int(R2[2 * x]) | (int(R2[2 * x + 1]) << 64)
     return R, dw.value
 
 

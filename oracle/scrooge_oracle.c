@@ -32,6 +32,10 @@
  *   window including the last; edits = number of non-M operations emitted;
  *   trailing text is free (text_end reports how much text was consumed).
  *
+ * Window widths: W up to 128.  A pattern-indexed bitvector is a uint64_t for
+ * W <= 64 and an unsigned __int128 above; the algorithm is written once, in
+ * oracle_width.inc, and instantiated for both types.
+ *
  * Operation codes: 0 = M (match), 1 = S (substitution), 2 = I (pattern
  * character not in text), 3 = D (text character not in pattern).
  *
@@ -80,52 +84,25 @@ static int encode_base(uint8_t c) {
     }
 }
 
-/* all-ones over the m_w low machine bits */
-static uint64_t width_mask(int mw) { return mw >= 64 ? ~0ULL : ((1ULL << mw) - 1ULL); }
+typedef struct {
+    int max_col, max_bit, max_row, min_row;
+} tb_reads;
 
-/* paper bit j of an m_w-bit vector; bit index m_w (one past the last pattern
- * character) reads as 0: the empty pattern suffix is always within distance. */
-static int pbit(uint64_t v, int j, int mw) {
-    if (j >= mw) return 0;
-    return (int)((v >> (mw - 1 - j)) & 1ULL);
-}
+#define BV uint64_t
+#define BVBITS 64
+#define SFX(x) x##_64
+#include "oracle_width.inc"
+#undef BV
+#undef BVBITS
+#undef SFX
 
-/* buildPatternMasks (Section 2.2.1): PM[X] has a 0 at bit j iff p[j] == X. */
-static void build_pattern_masks(const int8_t* p, int mw, uint64_t PM[4]) {
-    const uint64_t mask = width_mask(mw);
-    for (int x = 0; x < 4; x++) {
-        PM[x] = mask;
-        for (int j = 0; j < mw; j++)
-            if (p[j] == x) PM[x] &= ~(1ULL << (mw - 1 - j));
-    }
-}
-
-/* Algorithm 1 on one window.  p, t hold base codes.  R must hold
- * (nw+1)*(kw+1) words, R[i*(kw+1)+d].  Returns d_w, or -1 when no row
- * 0..kw has a 0 in the msb of its leftmost entry. */
-static int genasm_dc(const int8_t* p, int mw, const int8_t* t, int nw, int kw, uint64_t* R) {
-    const uint64_t mask = width_mask(mw);
-    const int K = kw + 1;
-    uint64_t PM[4];
-    build_pattern_masks(p, mw, PM);
-    /* right column: R[n][d] = 11...1 << d, restricted to m_w bits */
-    for (int d = 0; d <= kw; d++)
-        R[nw * K + d] = d >= 64 ? 0ULL : ((mask << d) & mask);
-    for (int i = nw - 1; i >= 0; i--) {
-        const uint64_t cur = PM[(int)t[i]];
-        R[i * K + 0] = ((R[(i + 1) * K + 0] << 1) | cur) & mask;
-        for (int d = 1; d <= kw; d++) {
-            const uint64_t I = (R[i * K + d - 1] << 1) & mask;
-            const uint64_t D = R[(i + 1) * K + d - 1];
-            const uint64_t S = (R[(i + 1) * K + d - 1] << 1) & mask;
-            const uint64_t M = ((R[(i + 1) * K + d] << 1) | cur) & mask;
-            R[i * K + d] = I & D & S & M;
-        }
-    }
-    for (int d = 0; d <= kw; d++)
-        if (pbit(R[d], 0, mw) == 0) return d;
-    return -1;
-}
+#define BV unsigned __int128
+#define BVBITS 128
+#define SFX(x) x##_128
+#include "oracle_width.inc"
+#undef BV
+#undef BVBITS
+#undef SFX
 
 /* Public: run Algorithm 1 on one window given as ASCII and return the table. */
 int or_dc_table(const uint8_t* pat, int32_t mw, const uint8_t* txt, int32_t nw, int32_t kw,
@@ -134,7 +111,27 @@ int or_dc_table(const uint8_t* pat, int32_t mw, const uint8_t* txt, int32_t nw, 
     int8_t p[64], t[64];
     for (int j = 0; j < mw; j++) { int c = encode_base(pat[j]); if (c < 0) return OR_EALPHABET; p[j] = (int8_t)c; }
     for (int i = 0; i < nw; i++) { int c = encode_base(txt[i]); if (c < 0) return OR_EALPHABET; t[i] = (int8_t)c; }
-    *dw = genasm_dc(p, mw, t, nw, kw, R);
+    *dw = genasm_dc_64(p, mw, t, nw, kw, R);
+    return OR_OK;
+}
+
+/* Public: the same for windows of up to 128 characters; entry (i, d) is
+ * returned as two words, R2[2*(i*(kw+1)+d)] = low 64 bits, [+1] = high. */
+int or_dc_table_wide(const uint8_t* pat, int32_t mw, const uint8_t* txt, int32_t nw, int32_t kw,
+                     uint64_t* R2, int32_t* dw) {
+    if (mw < 1 || mw > 128 || nw < 0 || nw > 128 || kw < 0 || kw > mw) return OR_EINVAL;
+    int8_t p[128], t[128];
+    for (int j = 0; j < mw; j++) { int c = encode_base(pat[j]); if (c < 0) return OR_EALPHABET; p[j] = (int8_t)c; }
+    for (int i = 0; i < nw; i++) { int c = encode_base(txt[i]); if (c < 0) return OR_EALPHABET; t[i] = (int8_t)c; }
+    const size_t cells = (size_t)(nw + 1) * (size_t)(kw + 1);
+    unsigned __int128* R = (unsigned __int128*)malloc(sizeof(unsigned __int128) * cells);
+    if (!R) return OR_ENOMEM;
+    *dw = genasm_dc_128(p, mw, t, nw, kw, R);
+    for (size_t x = 0; x < cells; x++) {
+        R2[2 * x] = (uint64_t)R[x];
+        R2[2 * x + 1] = (uint64_t)(R[x] >> 64);
+    }
+    free(R);
     return OR_OK;
 }
 
@@ -143,104 +140,25 @@ int or_pattern_masks(const uint8_t* pat, int32_t mw, uint64_t* PM) {
     if (mw < 1 || mw > 64) return OR_EINVAL;
     int8_t p[64];
     for (int j = 0; j < mw; j++) { int c = encode_base(pat[j]); if (c < 0) return OR_EALPHABET; p[j] = (int8_t)c; }
-    build_pattern_masks(p, mw, PM);
+    build_pattern_masks_64(p, mw, PM);
     return OR_OK;
 }
 
-typedef struct {
-    int max_col, max_bit, max_row, min_row;
-} tb_reads;
 
-static uint64_t tb_entry(const uint64_t* R, int K, int i, int d, int j, tb_reads* rd) {
-    if (i > rd->max_col) rd->max_col = i;
-    if (j > rd->max_bit) rd->max_bit = j;
-    if (d > rd->max_row) rd->max_row = d;
-    if (d < rd->min_row) rd->min_row = d;
-    return R[i * K + d];
-}
-
-/* Align one pair.  ops receives one byte per operation.  Returns OR_OK,
- * OR_NOT_ALIGNED or a negative error.  wrec (optional) receives one record
- * per window. */
+/* Align one pair with window W (1..128), overlap O and edit budget k: the
+ * 64-bit instantiation for W <= 64, the 128-bit one above.  Returns OR_OK,
+ * OR_NOT_ALIGNED or a negative error. */
 int or_align_pair(const uint8_t* pat, int32_t m, const uint8_t* txt, int32_t n,
                   int32_t W, int32_t O, int32_t k,
                   int32_t* edits_out, int32_t* text_end_out,
                   uint8_t* ops, int64_t ops_cap, int64_t* n_ops_out,
                   or_stats* st, or_window* wrec, int64_t wrec_cap, int64_t* n_wrec, int32_t pair_id) {
-    if (W < 1 || W > 64 || O < 0 || O >= W || k < 0 || k > W || m < 0 || n < 0) return OR_EINVAL;
-    int8_t* P = (int8_t*)malloc((size_t)m + 1);
-    int8_t* T = (int8_t*)malloc((size_t)n + 1);
-    uint64_t* R = (uint64_t*)malloc(sizeof(uint64_t) * 65 * 65);
-    if (!P || !T || !R) { free(P); free(T); free(R); return OR_ENOMEM; }
-    int rc = OR_OK;
-    for (int32_t x = 0; x < m && rc == OR_OK; x++) { int c = encode_base(pat[x]); if (c < 0) rc = OR_EALPHABET; else P[x] = (int8_t)c; }
-    for (int32_t x = 0; x < n && rc == OR_OK; x++) { int c = encode_base(txt[x]); if (c < 0) rc = OR_EALPHABET; else T[x] = (int8_t)c; }
-    int64_t nops = 0, nw_rec = 0;
-    int32_t edits = 0, p0 = 0, t0 = 0;
-    const int cap = W - O;
-    while (rc == OR_OK && p0 < m) {
-        const int mw = (m - p0) < W ? (m - p0) : W;
-        const int nw = (n - t0) < W ? (n - t0) : W;
-        const int kw = k < mw ? k : mw;
-        const int K = kw + 1;
-        const int8_t* p = P + p0;
-        const int8_t* t = T + t0;
-        const int dw = genasm_dc(p, mw, t, nw, kw, R);
-        const int drows = dw < 0 ? kw : dw;
-        if (st) {
-            st->windows++;
-            st->ops_alg += (int64_t)(drows + 1) + 2LL * nw + 7LL * nw * drows;
-            st->ops_genasm += (int64_t)(kw + 1) + 2LL * nw + 7LL * nw * kw;
-        }
-        if (dw < 0) { rc = OR_NOT_ALIGNED; break; }
-        /* GenASM-TB */
-        int i = 0, j = 0, d = dw, wedits = 0;
-        tb_reads rd = {-1, -1, -1, 1 << 30};
-        while (j < mw && i < cap && j < cap) {
-            int m_ok = 0, s_ok = 0, i_ok = 0, d_ok = 0;
-            if (i < nw && t[i] == p[j])
-                m_ok = pbit(tb_entry(R, K, i + 1, d, j + 1, &rd), j + 1, mw) == 0;
-            if (!m_ok && d > 0) {
-                if (i < nw) s_ok = pbit(tb_entry(R, K, i + 1, d - 1, j + 1, &rd), j + 1, mw) == 0;
-                if (!s_ok) i_ok = pbit(tb_entry(R, K, i, d - 1, j + 1, &rd), j + 1, mw) == 0;
-                if (!s_ok && !i_ok && i < nw) d_ok = pbit(tb_entry(R, K, i + 1, d - 1, j, &rd), j, mw) == 0;
-            }
-            int op;
-            if (m_ok) { op = OP_M; i++; j++; }
-            else if (s_ok) { op = OP_S; i++; j++; d--; }
-            else if (i_ok) { op = OP_I; j++; d--; }
-            else if (d_ok) { op = OP_D; i++; d--; }
-            else { rc = OR_EINTERNAL; break; }
-            if (op != OP_M) wedits++;
-            if (nops >= ops_cap) { rc = OR_ERANGE; break; }
-            ops[nops++] = (uint8_t)op;
-            if (st) st->tb_steps++;
-        }
-        if (rc != OR_OK) break;
-        if (st) {
-            if (rd.max_col > st->max_col_read) st->max_col_read = rd.max_col;
-            if (rd.max_bit > st->max_bit_read) st->max_bit_read = rd.max_bit;
-            if (rd.max_row >= 0 && rd.max_row - dw > st->max_row_above_dw) st->max_row_above_dw = rd.max_row - dw;
-            if (rd.min_row <= 64 && dw - rd.min_row > st->max_rows_below_dw) st->max_rows_below_dw = dw - rd.min_row;
-        }
-        if (wrec && nw_rec < wrec_cap) {
-            or_window* w = &wrec[nw_rec];
-            w->pair = pair_id; w->p0 = p0; w->t0 = t0; w->m_w = mw; w->n_w = nw; w->k_w = kw;
-            w->d_w = dw; w->adv_p = j; w->adv_t = i; w->edits = wedits;
-        }
-        nw_rec++;
-        edits += wedits;
-        p0 += j;
-        t0 += i;
-    }
-    if (n_wrec) *n_wrec = nw_rec;
-    if (rc == OR_OK) {
-        *edits_out = edits; *text_end_out = t0; *n_ops_out = nops;
-    } else {
-        *edits_out = -1; *text_end_out = -1; *n_ops_out = 0;
-    }
-    free(P); free(T); free(R);
-    return rc;
+    if (W < 1 || W > 128 || O < 0 || O >= W || k < 0 || k > W || m < 0 || n < 0) return OR_EINVAL;
+    if (W <= 64)
+        return align_pair_64(pat, m, txt, n, W, O, k, edits_out, text_end_out, ops, ops_cap, n_ops_out, st, wrec,
+                             wrec_cap, n_wrec, pair_id);
+    return align_pair_128(pat, m, txt, n, W, O, k, edits_out, text_end_out, ops, ops_cap, n_ops_out, st, wrec,
+                          wrec_cap, n_wrec, pair_id);
 }
 
 typedef struct {
@@ -296,7 +214,7 @@ int or_align_batch(int32_t npairs, const uint8_t* pat, const int64_t* pat_off,
                    int32_t* edits, int32_t* text_end, int32_t* status,
                    uint8_t* ops, const int64_t* ops_off, int64_t* n_ops, or_stats* total) {
     if (npairs < 0 || nthreads < 1 || nthreads > 1024) return OR_EINVAL;
-    if (W < 1 || W > 64 || O < 0 || O >= W || k < 0 || k > W) return OR_EINVAL;
+    if (W < 1 || W > 128 || O < 0 || O >= W || k < 0 || k > W) return OR_EINVAL;
     batch_job J;
     memset(&J, 0, sizeof J);
     J.npairs = npairs; J.pat = pat; J.txt = txt; J.pat_off = pat_off; J.txt_off = txt_off; J.ops_off = ops_off;

@@ -15,7 +15,7 @@ import oracle
 from paper_2208_09985_amd import synth
 from tests import refs
 
-GEOMETRIES = ((64, 24), (64, 33), (64, 16), (64, 40), (32, 8))
+GEOMETRIES = ((64, 24), (64, 33), (64, 16), (64, 40), (32, 8), (96, 32), (128, 24), (128, 64))
 PAIRS = range(int(os.environ.get("SCG_ACCURACY_PAIRS", "6")))
 
 

@@ -63,9 +63,9 @@ def test_worked_example_fig1():
 
 # --- Theorem 1: every bit of every entry ---------------------------------------------------
 
-def _check_theorem1(pattern, text, k):
+def _check_theorem1(pattern, text, k, wide=False):
     m, n = len(pattern), len(text)
-    R, d = oracle.dc_table(pattern, text, k)
+    R, d = (oracle.dc_table_wide if wide else oracle.dc_table)(pattern, text, k)
     D = refs.suffix_dp(pattern, text)
     for i in range(n + 1):
         for dd in range(k + 1):
@@ -109,6 +109,28 @@ def test_theorem1_full_width_windows():
     _check_theorem1(rand_seq(rng, 64), rand_seq(rng, 64), 64)
 
 
+def test_theorem1_windows_wider_than_64():
+    # the 128-bit instantiation: windows of 65..128 characters, every bit
+    rng = np.random.default_rng(21)
+    for m, n, rate in ((65, 70, 0.1), (96, 96, 0.15), (128, 128, 0.05), (128, 128, 0.3), (100, 0, 0.0)):
+        p = rand_seq(rng, m)
+        t = mutate(rng, p + rand_seq(rng, 16), rate)[:n]
+        _check_theorem1(p, t, min(m, 40), wide=True)
+
+
+def test_wide_instantiation_agrees_with_64_bit_one():
+    # windows of up to 64 characters give the same table in both widths
+    rng = np.random.default_rng(22)
+    for _ in range(40):
+        m, n = int(rng.integers(1, 65)), int(rng.integers(0, 65))
+        p, t = rand_seq(rng, m), mutate(rng, rand_seq(rng, n), 0.2)[:n]
+        k = int(rng.integers(0, m + 1))
+        R64, d64 = oracle.dc_table(p, t, k)
+        R128, d128 = oracle.dc_table_wide(p, t, k)
+        assert d64 == d128
+        assert all(int(R64.flat[x]) == R128.flat[x] for x in range(R64.size))
+
+
 # --- Section 2.2.3: a single window with no overlap is the exact optimum ---------------------
 
 def test_single_window_o0_equals_bruteforce_optimum():
@@ -121,6 +143,20 @@ def test_single_window_o0_equals_bruteforce_optimum():
             r = oracle.align_pair(p, t, W, 0, W)
             assert r["status"] == 0
             assert r["edits"] == refs.shw_bruteforce(p, t), (W, p, t)
+            e, used = refs.replay(p, t, r["ops"])
+            assert (e, used) == (r["edits"], r["text_end"])
+
+
+def test_single_wide_window_o0_equals_optimum():
+    rng = np.random.default_rng(23)
+    for W in (65, 96, 128):
+        for _ in range(12):
+            m, n = int(rng.integers(1, W + 1)), int(rng.integers(0, W + 1))
+            p = rand_seq(rng, m)
+            t = mutate(rng, p, 0.2)[:n] if rng.random() < 0.7 else rand_seq(rng, n)
+            r = oracle.align_pair(p, t, W, 0, W)
+            assert r["status"] == 0
+            assert r["edits"] == refs.suffix_dp(p, t)[0][0], (W, p, t)
             e, used = refs.replay(p, t, r["ops"])
             assert (e, used) == (r["edits"], r["text_end"])
 
@@ -150,7 +186,7 @@ def test_replay_long_sample():
 
 def test_windowed_edits_bounded_below_by_optimum():
     rng = np.random.default_rng(4)
-    for W, O in ((64, 24), (16, 9), (8, 3)):
+    for W, O in ((64, 24), (16, 9), (8, 3), (128, 24), (96, 33)):
         for _ in range(25):
             p = rand_seq(rng, int(rng.integers(1, 90)))
             t = mutate(rng, p, 0.15)
@@ -207,7 +243,7 @@ def test_full_window_op_count_28865():
 
 # --- Sections 2.4.2 / 2.4.3 and supplementary S1: what traceback reads ---------------------
 
-@pytest.mark.parametrize("W,O", [(4, 3), (64, 24), (64, 33), (32, 17)])
+@pytest.mark.parametrize("W,O", [(4, 3), (64, 24), (64, 33), (32, 17), (128, 24), (96, 40)])
 def test_traceback_reads_stay_in_dent_region(W, O):
     rng = np.random.default_rng(9)
     st_all = []
