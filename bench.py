@@ -258,14 +258,14 @@ def main():
         workloads[name] = entry
         del wb
         # window geometry on the headline batch: throughput and windowed edit counts per (W, O);
-        # W - O <= 31 stores 32-bit entries
+        # W - O <= 31 stores 32-bit entries, W > 64 runs 128-bit bitvectors
         sweep = {}
-        for (W, O) in ((64, 24), (64, 33), (64, 16), (64, 40), (32, 8)):
+        for (W, O) in ((64, 24), (64, 33), (64, 16), (64, 40), (32, 8), (96, 32), (128, 24), (128, 64)):
             sms, sst, sres = measure(batch, f"window sweep W={W} O={O}", api.params(W=W, O=O, k=W, mode="plain"), 5, 1)
             e = summary(batch, sms, sst)
             ach = sst.ops_alg / (sst.kernel_ms_avg / 1e3) / 1e12
             e.update(windows=int(sst.windows), frac=round(ach / PEAK_T64OPS, 5),
-                     stored_entry_bits=32 if W - O <= 31 else 64,
+                     stored_entry_bits=32 if W - O <= 31 else (64 if W <= 64 else 128),
                      mean_edits=round(float(np.mean(sres.edits[sres.status == 0])), 2),
                      aligned=int(np.sum(sres.status == 0)))
             sweep[f"W{W}_O{O}"] = e

@@ -16,7 +16,10 @@
  *   - Sequences are ASCII A/C/G/T (either case).  Anything else is an input
  *     error: host input is rejected at batch creation (SCG_EALPHABET); device
  *     input marks the offending pair with SCG_PAIR_BAD_INPUT.
- *   - Windows: 1 <= W <= 64, 0 <= O < W, 0 <= k <= W (else SCG_EINVAL).
+ *   - Windows: 1 <= W <= 64, 0 <= O < W, 0 <= k <= W (else SCG_EINVAL);
+ *     plain mode also takes 64 < W <= 128 (128-bit bitvectors, column
+ *     blocks, no yields or ablation flags; anything else with W > 64 is
+ *     SCG_EINVAL).
  *     Window w aligns pattern[p0, p0+m_w) with text[t0, t0+n_w), m_w =
  *     min(W, m-p0), n_w = min(W, n-t0), allowing k_w = min(k, m_w) edits.
  *     Traceback stops once W-O characters of text or pattern are consumed

@@ -17,7 +17,7 @@ import tempfile
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libscrooge_hip.so")
-SOURCES = ["pack.hip", "align.hip", "align_cols.hip", "mlp.hip", "capi.cpp"]
+SOURCES = ["pack.hip", "align.hip", "align_cols.hip", "align_wide.hip", "mlp.hip", "capi.cpp"]
 ARCH = os.environ.get("SCG_OFFLOAD_ARCH", "gfx950")
 
 HIPCC_FLAGS = [

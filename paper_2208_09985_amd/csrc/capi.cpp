@@ -58,6 +58,7 @@ struct scg_batch {
     uint64_t* dent_d = nullptr;     // column-block kernel: stored rows per group
     int dstride = 0;
     bool cols = false;              // column-block kernel selected
+    bool wide = false;              // windows of 65..128 characters (wide_kernel)
     // launch shape
     int ns = 1;
     int grid = 1;
@@ -107,7 +108,11 @@ bool valid_base(uint8_t c) {
 
 int check_params(const scg_params* p) {
     if (!p) return SCG_EINVAL;
-    if (p->W < 1 || p->W > 64 || p->O < 0 || p->O >= p->W || p->k < 0 || p->k > p->W) return SCG_EINVAL;
+    if (p->W < 1 || p->W > 128 || p->O < 0 || p->O >= p->W || p->k < 0 || p->k > p->W) return SCG_EINVAL;
+    // windows wider than 64: plain mode in the column-block form only, no yields or ablations
+    if (p->W > 64 && (p->mode != SCG_MODE_PLAIN || p->kernel == SCG_KERNEL_ROWS || p->yield_chars > 0 ||
+                      (p->flags & (SCG_FLAG_NO_EARLY_TERMINATION | SCG_FLAG_STORE_ALL_COLUMNS))))
+        return SCG_EINVAL;
     if (p->mode < SCG_MODE_PLAIN || p->mode > SCG_MODE_FIXED) return SCG_EINVAL;
     // column blocks without a learned budget also run 32 windows per wavefront
     const bool cols = p->kernel == SCG_KERNEL_COLUMNS || (p->kernel == SCG_KERNEL_AUTO && p->mode == SCG_MODE_PLAIN);
@@ -199,7 +204,8 @@ int enqueue_run(scg_batch* b, hipStream_t s, int32_t* edits, int32_t* text_end, 
     a.dstride = b->dstride;
     a.no_et = (b->p.flags & SCG_FLAG_NO_EARLY_TERMINATION) ? 1 : 0;
     if (b->npairs > 0) {
-        if (b->cols) HIP_TRY(launch_align_cols(a, b->grid, b->ns, b->lds, s));
+        if (b->wide) HIP_TRY(launch_align_wide(a, b->grid, b->ns, s));
+        else if (b->cols) HIP_TRY(launch_align_cols(a, b->grid, b->ns, b->lds, s));
         else HIP_TRY(launch_align(a, b->grid, b->lds, s));
     }
     if (with_events) {
@@ -375,7 +381,11 @@ int scg_batch_create(scg_ctx* c, const scg_params* params, int32_t npairs, const
     // automatic yields: the row-lane kernel hands pairs back every 1280
     // pattern characters; the column-block kernel keeps them (its passes
     // advance every pair by one window, so pairs finish together anyway)
-    if (b->p.yield_chars < 0) b->p.yield_chars = b->cols ? 0 : 1280;
+    b->wide = params->W > 64;
+    if (b->wide) b->cols = false;
+    if (b->p.yield_chars < 0) b->p.yield_chars = (b->cols || b->wide) ? 0 : 1280;
+    // windows wider than 64 read three planes words from their start: two padding words
+    const int pad_words = b->wide ? 2 : 1;
     // host-side tables
     std::vector<int64_t> pw(npairs + 1), tw(npairs + 1);
     std::vector<int32_t> pl(npairs), tl(npairs);
@@ -384,8 +394,8 @@ int scg_batch_create(scg_ctx* c, const scg_params* params, int32_t npairs, const
     for (int32_t i = 0; i < npairs; ++i) {
         pl[i] = (int32_t)(pat_off[i + 1] - pat_off[i]);
         tl[i] = (int32_t)(txt_off[i + 1] - txt_off[i]);
-        pw[i + 1] = pw[i] + (pl[i] + 63) / 64 + 1;   // + one padding Plane2
-        tw[i + 1] = tw[i] + (tl[i] + 63) / 64 + 1;
+        pw[i + 1] = pw[i] + (pl[i] + 63) / 64 + pad_words;   // + zero padding Plane2s
+        tw[i + 1] = tw[i] + (tl[i] + 63) / 64 + pad_words;
         b->runs_off_h[i + 1] = b->runs_off_h[i] + pl[i] + tl[i] + 1;
     }
     b->pwords = pw[npairs];
@@ -442,7 +452,12 @@ int scg_batch_create(scg_ctx* c, const scg_params* params, int32_t npairs, const
     // launch shape
     const bool learned = params->mode == SCG_MODE_LEARNED;
     int per_cu;
-    if (b->cols) {
+    if (b->wide) {
+        // 4 or 8 windows per wavefront (16 or 8 lanes of 8 or 16 columns each)
+        b->ns = params->slots > 4 ? 8 : 4;
+        b->lds = 0;
+        per_cu = wide_max_blocks_per_cu(b->ns);
+    } else if (b->cols) {
         // windows per wavefront: 4, 8 or 16; automatic = enough wavefronts to
         // give every SIMD two of them
         if (params->slots > 0)
@@ -459,6 +474,11 @@ int scg_batch_create(scg_ctx* c, const scg_params* params, int32_t npairs, const
     b->grid = std::max(1, per_cu * c->num_cu);
     const int64_t need = (npairs + b->ns - 1) / b->ns;   // more wavefronts than slots-worth of pairs idle
     if (b->grid > need) b->grid = (int)std::max<int64_t>(1, need);
+    if (b->wide && npairs > 0) {
+        const int cap = params->W - params->O;
+        b->dstride = wide_dent_stride(cap, b->ns);
+        if ((rc = dev_alloc(&b->dent_d, wide_dent_bytes(b->grid, cap, b->ns) / sizeof(uint64_t)))) return fail(rc);
+    }
     if (b->cols && npairs > 0) {
         const int cap = params->W - params->O;
         // stored columns 0..cap (DENT), or all of them for the ablation

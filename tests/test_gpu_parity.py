@@ -257,3 +257,35 @@ def test_one_shot_batch_call(ctx):
         res = api.align_batch_once(ctx, b, host=host)
         compare(b, res, ref, f"one-shot host={host}")
         assert res.stats.windows > 0 and res.stats.kernel_ms > 0
+
+
+@pytest.mark.parametrize("W,O,k,slots", [(128, 24, 128, 0), (128, 64, 128, 8), (96, 32, 96, 0), (65, 0, 65, 4),
+                                         (128, 127, 128, 0), (100, 40, 30, 8), (128, 24, 5, 0)])
+def test_wide_windows(ctx, W, O, k, slots):
+    # windows of 65..128 characters (wide kernel), against the oracle's 128-bit instantiation
+    rng = np.random.default_rng(W * 1000 + O * 10 + k)
+    pats, txts = [], []
+    for i in range(120):
+        m = int(rng.integers(0, 700)) if i % 10 else int(rng.integers(0, 3))
+        p = synth.ALPHABET[rng.integers(0, 4, m)]
+        t = p.copy()
+        for _ in range(int(m * rng.uniform(0, 0.3))):
+            pos = int(rng.integers(0, max(1, len(t))))
+            r = rng.random()
+            if r < 0.33 and len(t):
+                t[pos] = synth.ALPHABET[rng.integers(0, 4)]
+            elif r < 0.66:
+                t = np.insert(t, pos, synth.ALPHABET[rng.integers(0, 4, int(rng.integers(1, 6)))])
+            elif len(t):
+                t = np.delete(t, slice(pos, pos + int(rng.integers(1, 6))))
+        if i % 17 == 0:
+            t = synth.ALPHABET[rng.integers(0, 4, int(rng.integers(0, 300)))]   # unrelated text
+        pats.append(p.tobytes())
+        txts.append(t.tobytes())
+    b = synth.from_lists(pats, txts)
+    check(ctx, b, W=W, O=O, k=k, what=f"wide W{W}O{O}k{k} slots{slots}", kernels=("columns",), slots=slots)
+
+
+def test_wide_windows_long_reads(ctx):
+    b = synth.make_batch("long_10kbp", indices=range(300, 316))
+    check(ctx, b, W=128, O=24, k=128, what="wide long_10kbp", kernels=("columns",))
