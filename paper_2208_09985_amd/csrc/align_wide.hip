@@ -83,8 +83,10 @@ __device__ __forceinline__ uint32_t word_of(V128 v, int k) {
     return (uint32_t)((k < 2 ? v.lo : v.hi) >> (32 * (k & 1)));
 }
 
+// Occupancy target: three wavefronts per SIMD with 4 windows each (168
+// VGPRs), two with 8 (256), so that 10,000 pairs are resident at once.
 template <int NG>
-__global__ __launch_bounds__(64) void wide_kernel(const AlignArgs a) {
+__global__ __launch_bounds__(64, NG == 4 ? 3 : 2) void wide_kernel(const AlignArgs a) {
     constexpr int L = 64 / NG;      // lanes per window
     constexpr int CB = 128 / L;     // columns per lane
     __shared__ GroupRecW grec[NG];
@@ -177,9 +179,13 @@ __global__ __launch_bounds__(64) void wide_kernel(const AlignArgs a) {
         __syncthreads();
 
         // ---- 3. every lane of a group with a new window builds its columns ----
+        // A pass always runs its windows to the end, so no row survives a
+        // round: every lane rebuilds its columns (from the group's current
+        // record; only a fresh window's are used), which keeps the row and the
+        // match masks out of the registers live across rounds.
         {
             const GroupRecW r = grec[g];
-            if (r.fresh) {
+            {
                 // bits j >= m_w of every entry and match mask are 1 (the empty pattern suffix)
                 const V128 beyond{r.m_w >= 64 ? 0ull : (~0ull << r.m_w),
                                   r.m_w >= 128 ? 0ull : (r.m_w <= 64 ? ~0ull : (~0ull << (r.m_w - 64)))};
@@ -206,9 +212,11 @@ __global__ __launch_bounds__(64) void wide_kernel(const AlignArgs a) {
                     zr[k] = word_of(z, k);
                 }
                 dl = q - (L - 1);
-                full = r.full;
-                dw = -1;
-                gst = W_RUN;
+                if (r.fresh) {
+                    full = r.full;
+                    dw = -1;
+                    gst = W_RUN;
+                }
             }
         }
 

@@ -453,8 +453,10 @@ int scg_batch_create(scg_ctx* c, const scg_params* params, int32_t npairs, const
     const bool learned = params->mode == SCG_MODE_LEARNED;
     int per_cu;
     if (b->wide) {
-        // 4 or 8 windows per wavefront (16 or 8 lanes of 8 or 16 columns each)
-        b->ns = params->slots > 4 ? 8 : 4;
+        // 4 or 8 windows per wavefront (16 or 8 lanes of 8 or 16 columns each);
+        // automatic: 8 once that still gives every SIMD a wavefront
+        if (params->slots > 0) b->ns = params->slots > 4 ? 8 : 4;
+        else b->ns = npairs >= 8 * c->num_cu ? 8 : 4;
         b->lds = 0;
         per_cu = wide_max_blocks_per_cu(b->ns);
     } else if (b->cols) {
