@@ -66,7 +66,7 @@ constexpr int kStoredRows = 64;    // rows 0..63 are kept for traceback
 // waits for it), DONE when d_w is known (or no row up to k_w has it), TB
 // while its traceback runs (possibly over several rounds).
 enum : int { G_EMPTY = 0, G_RUN = 1, G_DONE = 2, G_OVER = 3, G_TB = 4 };
-constexpr int kTbEvents = 24;      // traceback events (match runs or edit steps) per round
+constexpr int kTbEvents = 40;      // traceback events (match run + edit step) per round
 constexpr int kWaitRows = 16;      // learned mode: largest predicted budget a pass waits for
 enum : int { CMD_NONE = 0, CMD_FRESH = 1, CMD_RESUME = 2 };
 
@@ -320,9 +320,9 @@ __global__ __launch_bounds__(64) void cols_kernel(const AlignArgs a) {
 
         // ---- 6. traceback of finished windows, advance, output ----
         // Finished windows start their traceback; every traceback in the
-        // wavefront then runs at most kTbEvents match runs / edit steps in
-        // this round and continues in the next one, so one long path does
-        // not hold the whole wavefront.
+        // wavefront then runs at most kTbEvents (match run, edit step)
+        // events in this round and continues in the next one, so one very
+        // long path does not hold the whole wavefront.
         if (slot && gst == G_DONE) {
             c_rows += (unsigned long long)(dw < 0 || a.no_et ? full : dw + 1);
             tb_d = dw;

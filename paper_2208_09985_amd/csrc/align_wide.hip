@@ -27,7 +27,7 @@ namespace {
 using namespace colblock;
 
 constexpr int kRowsW = 128;       // rows 0..127 are kept for traceback
-constexpr int kTbEventsW = 32;    // traceback events per round
+constexpr int kTbEventsW = 64;    // traceback events per round
 enum : int { W_EMPTY = 0, W_RUN = 1, W_DONE = 2, W_TB = 4 };
 
 // A 128-bit pattern-indexed vector: bit j in lo for j < 64, in hi otherwise.
