@@ -349,34 +349,40 @@ __global__ __launch_bounds__(64) void cols_kernel(const AlignArgs a) {
             const bool tracing = slot && gst == G_TB;
             const GroupRec r = grec[g];
             const int jlim = min(mw, cap);
+            const int ilim = min(nw, cap);              // a match run stops at the text window's end and at the cap
+            uint32_t* const rout = a.runs + roff;       // the pair's run list (m + n + 1 >= 1 entries)
+            const int rlast = (int)rcap - 1;
             bool fin = !tracing;
             for (int ev = 0; ev < kTbEvents && __ballot(!fin) != 0; ++ev) {
                 if (!fin) {
-                    // match run at (ti, tj); characters past n_w never match
+                    // match run at (tb_i, tb_j); characters past n_w never match
                     const uint64_t x = ((r.thi >> tb_i) ^ (r.phi >> tb_j)) | ((r.tlo >> tb_i) ^ (r.plo >> tb_j));
                     int L = x ? (int)__builtin_ctzll(x) : 64;
-                    L = min(L, min(nw - tb_i, min(jlim - tb_j, cap - tb_i)));
-                    L = max(L, 0);
-                    emit_run(0, L, cur_op, cur_len, nruns, a.runs, roff, rcap);
-                    tb_i += L;
-                    tb_j += L;
-                    fin = tb_j >= jlim || tb_i >= cap;
-                }
-                if (!fin) {
-                    // edit step: bits tj, tj+1 of row td-1 at columns ti and ti+1
-                    const int ti = tb_i, tj = tb_j, td = tb_d;
-                    const size_t ro = (size_t)(max(td, 1) - 1) * stride;
-                    const int c0 = min(ti, stride - 1), c1 = min(ti + 1, stride - 1);
+                    L = max(min(L, min(ilim - tb_i, jlim - tb_j)), 0);
+                    const int ti = tb_i + L, tj = tb_j + L, td = tb_d;
+                    // edit step at (ti, tj, td): bits tj, tj+1 of row td-1 at columns ti and ti+1.
+                    // The loads go out first; the run bookkeeping below overlaps them.
+                    const int ro = (max(td, 1) - 1) * stride;
+                    const int c0 = ro + min(ti, stride - 1), c1 = ro + min(ti + 1, stride - 1);
                     uint64_t v0, v1;
                     if (NARROW) {
-                        const uint32_t* rowp = reinterpret_cast<const uint32_t*>(gdent) + ro;
+                        const uint32_t* rowp = reinterpret_cast<const uint32_t*>(gdent);
                         v0 = rowp[c0];
                         v1 = rowp[c1];
                     } else {
-                        const uint64_t* rowp = gdent + ro;
-                        v0 = rowp[c0];
-                        v1 = rowp[c1];
+                        v0 = gdent[c0];
+                        v1 = gdent[c1];
                     }
+                    // the run list always holds the open run at index nruns, so
+                    // extending or starting a run is one unconditional store
+                    {
+                        const bool same = cur_op == 0;
+                        nruns += (!same && cur_len > 0 && L > 0) ? 1 : 0;
+                        cur_len = L == 0 ? cur_len : (same ? cur_len + L : L);
+                        cur_op = L == 0 ? cur_op : 0;
+                        rout[min(nruns, rlast)] = ((uint32_t)cur_len << 2) | (uint32_t)cur_op;
+                    }
+                    const bool edit = !(tj >= jlim || ti >= cap);
                     const uint64_t rc = z_init(mw, td - 1);
                     const uint64_t za = ti < nw ? v0 : rc;        // Z[ti][td-1]
                     const uint64_t zb = ti + 1 < nw ? v1 : rc;    // Z[ti+1][td-1]
@@ -384,14 +390,20 @@ __global__ __launch_bounds__(64) void cols_kernel(const AlignArgs a) {
                     const int sb = has_t & zbit(zb, tj + 1);
                     const int ib = zbit(za, tj + 1);
                     const int db = has_t & zbit(zb, tj);
-                    tb_bad |= (td <= 0) | !(sb | ib | db);
                     const int op = sb ? 1 : (ib ? 2 : 3);
-                    tb_i += op != 2;
-                    tb_j += op != 3;
-                    tb_d -= 1;
-                    tb_e += 1;
-                    emit_run(op, 1, cur_op, cur_len, nruns, a.runs, roff, rcap);
-                    fin = tb_j >= jlim || tb_i >= cap || tb_bad;
+                    tb_bad |= edit & ((td <= 0) | !(sb | ib | db));
+                    tb_i = ti + (edit && op != 2 ? 1 : 0);
+                    tb_j = tj + (edit && op != 3 ? 1 : 0);
+                    tb_d = td - (edit ? 1 : 0);
+                    tb_e += edit ? 1 : 0;
+                    {
+                        const bool same = cur_op == op;
+                        nruns += (edit && !same && cur_len > 0) ? 1 : 0;
+                        cur_len = !edit ? cur_len : (same ? cur_len + 1 : 1);
+                        cur_op = !edit ? cur_op : op;
+                        rout[min(nruns, rlast)] = ((uint32_t)cur_len << 2) | (uint32_t)cur_op;
+                    }
+                    fin = !edit || tb_j >= jlim || tb_i >= cap || tb_bad;
                 }
             }
             if (tracing && fin) {
@@ -401,10 +413,7 @@ __global__ __launch_bounds__(64) void cols_kernel(const AlignArgs a) {
                 t0 += tb_i;
                 gst = G_EMPTY;
                 if (tb_bad || p0 >= m) {
-                    if (cur_len > 0) {
-                        if (nruns < rcap) a.runs[roff + nruns] = ((uint32_t)cur_len << 2) | (uint32_t)cur_op;
-                        ++nruns;
-                    }
+                    nruns += cur_len > 0 ? 1 : 0;   // the open run is already in the list
                     const bool ok = !tb_bad && nruns <= rcap;
                     if (!ok) c_err += 1;
                     a.edits[pair] = ok ? edits : -1;
