@@ -90,7 +90,14 @@ __global__ __launch_bounds__(64) void cols_kernel(const AlignArgs a) {
     const uint64_t gbit = 1ull << (lane - q);   // the group's slot lane in a ballot
     const int cap = a.cap;
     const int stride = a.dstride;
-    uint64_t* const gdent = a.dent + ((size_t)blockIdx.x * NG + g) * (size_t)(kStoredRows * stride);
+    // The block's stored rows start at a wavefront-uniform address; a lane reaches
+    // its group's entries with a 32-bit byte offset (a group holds 64 rows of
+    // `stride` entries of at most 8 bytes).
+    constexpr uint32_t ESZ = NARROW ? 4u : 8u;   // bytes per stored entry
+    char* const bdent = reinterpret_cast<char*>(a.dent + (size_t)blockIdx.x * NG * (size_t)(kStoredRows * stride));
+    const uint32_t gbyte = (uint32_t)(g * kStoredRows * stride) * 8u;
+    const uint32_t qbyte = gbyte + (uint32_t)(CB * q) * ESZ;   // the lane's first column in row 0
+    const uint32_t rowbytes = (uint32_t)stride * ESZ;
     const bool storer = CB * q < stride;
 
     if (lane < NG) grec[lane] = GroupRec{0, 0, 0, 0, 0, 0, 0, 0, CMD_NONE, 0};
@@ -287,12 +294,11 @@ __global__ __launch_bounds__(64) void cols_kernel(const AlignArgs a) {
             }
             // keep the row for traceback
             if (computing && storer && dl >= 0 && dl < kStoredRows) {
+                uint4* row = reinterpret_cast<uint4*>(bdent + (qbyte + __umul24((uint32_t)dl, rowbytes)));
                 if (NARROW) {
-                    uint4* row = reinterpret_cast<uint4*>(reinterpret_cast<uint32_t*>(gdent) + (size_t)dl * stride + CB * q);
 #pragma unroll
                     for (int t = 0; t < CB; t += 4) row[t >> 2] = uint4{A.lo[t], A.lo[t + 1], A.lo[t + 2], A.lo[t + 3]};
                 } else {
-                    uint4* row = reinterpret_cast<uint4*>(gdent + (size_t)dl * stride + CB * q);
 #pragma unroll
                     for (int t = 0; t < CB; t += 2) row[t >> 1] = uint4{A.lo[t], A.hi[t], A.lo[t + 1], A.hi[t + 1]};
                 }
@@ -362,16 +368,16 @@ __global__ __launch_bounds__(64) void cols_kernel(const AlignArgs a) {
                     const int ti = tb_i + L, tj = tb_j + L, td = tb_d;
                     // edit step at (ti, tj, td): bits tj, tj+1 of row td-1 at columns ti and ti+1.
                     // The loads go out first; the run bookkeeping below overlaps them.
-                    const int ro = (max(td, 1) - 1) * stride;
-                    const int c0 = ro + min(ti, stride - 1), c1 = ro + min(ti + 1, stride - 1);
+                    const uint32_t ro = gbyte + __umul24((uint32_t)(max(td, 1) - 1), rowbytes);
+                    const char* const e0 = bdent + (ro + (uint32_t)min(ti, stride - 1) * ESZ);
+                    const char* const e1 = bdent + (ro + (uint32_t)min(ti + 1, stride - 1) * ESZ);
                     uint64_t v0, v1;
                     if (NARROW) {
-                        const uint32_t* rowp = reinterpret_cast<const uint32_t*>(gdent);
-                        v0 = rowp[c0];
-                        v1 = rowp[c1];
+                        v0 = *reinterpret_cast<const uint32_t*>(e0);
+                        v1 = *reinterpret_cast<const uint32_t*>(e1);
                     } else {
-                        v0 = gdent[c0];
-                        v1 = gdent[c1];
+                        v0 = *reinterpret_cast<const uint64_t*>(e0);
+                        v1 = *reinterpret_cast<const uint64_t*>(e1);
                     }
                     // the run list always holds the open run at index nruns, so
                     // extending or starting a run is one unconditional store

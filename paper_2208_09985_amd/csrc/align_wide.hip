@@ -96,7 +96,12 @@ __global__ __launch_bounds__(64, NG == 4 ? 3 : 2) void wide_kernel(const AlignAr
     const uint64_t gbit = 1ull << (lane - q);   // the group's slot lane in a ballot
     const int cap = a.cap;
     const int stride = a.dstride;               // stored entries per row (16 bytes each)
-    uint4* const gdent = reinterpret_cast<uint4*>(a.dent) + ((size_t)blockIdx.x * NG + g) * (size_t)(kRowsW * stride);
+    // the block's stored rows start at a wavefront-uniform address; a lane reaches its
+    // group's entries with a 32-bit byte offset (a group holds 128 rows of `stride` entries)
+    char* const bdent = reinterpret_cast<char*>(reinterpret_cast<uint4*>(a.dent) + (size_t)blockIdx.x * NG * (size_t)(kRowsW * stride));
+    const uint32_t gbyte = (uint32_t)(g * kRowsW * stride) * 16u;
+    const uint32_t qbyte = gbyte + (uint32_t)(CB * q) * 16u;   // the lane's first column in row 0
+    const uint32_t rowbytes = (uint32_t)stride * 16u;
     const bool storer = CB * q < stride;
 
     if (lane < NG) grec[lane] = GroupRecW{{0, 0}, {0, 0}, {0, 0}, {0, 0}, 0, 0, 0, 0};
@@ -240,30 +245,39 @@ __global__ __launch_bounds__(64, NG == 4 ? 3 : 2) void wide_kernel(const AlignAr
                 const uint32_t v = from_upper_lane(A[k][0]);
                 nb[k] = q == L - 1 ? zr[k] : v;
             }
-            // I, S and D terms from row d-1, ascending columns (each column still
-            // sees its right neighbour's row d-1); register-tied
+            // I, S and D terms from row d-1: with S[t] = Z[t] >> 1 | cin they are
+            // S[t] | S[t+1] | Z[t+1].  Ascending columns (each column still sees its
+            // right neighbour's row d-1), S[t+1] carried to the next column; register-tied
+            uint32_t s0, s1, s2, s3;
+            asm volatile("v_alignbit_b32 %[s0], %[z1], %[z0], 1\n\t"
+                         "v_alignbit_b32 %[s1], %[z2], %[z1], 1\n\t"
+                         "v_alignbit_b32 %[s2], %[z3], %[z2], 1\n\t"
+                         "v_alignbit_b32 %[s3], %[cin], %[z3], 1"
+                         : [s0] "=&v"(s0), [s1] "=&v"(s1), [s2] "=&v"(s2), [s3] "=&v"(s3)
+                         : [z0] "v"(A[0][0]), [z1] "v"(A[1][0]), [z2] "v"(A[2][0]), [z3] "v"(A[3][0]), [cin] "v"(cin));
 #pragma unroll
             for (int t = 0; t < CB; ++t) {
                 const uint32_t x0 = t < CB - 1 ? A[0][t + 1] : nbs[0];
                 const uint32_t x1 = t < CB - 1 ? A[1][t + 1] : nbs[1];
                 const uint32_t x2 = t < CB - 1 ? A[2][t + 1] : nbs[2];
                 const uint32_t x3 = t < CB - 1 ? A[3][t + 1] : nbs[3];
-                uint32_t u0, u1, u2, u3;
-                asm volatile("v_or_b32 %[u0], %[p0], %[x0]\n\t"
-                             "v_or_b32 %[u1], %[p1], %[x1]\n\t"
-                             "v_or_b32 %[u2], %[p2], %[x2]\n\t"
-                             "v_or_b32 %[u3], %[p3], %[x3]\n\t"
-                             "v_alignbit_b32 %[u0], %[u1], %[u0], 1\n\t"
-                             "v_alignbit_b32 %[u1], %[u2], %[u1], 1\n\t"
-                             "v_alignbit_b32 %[u2], %[u3], %[u2], 1\n\t"
-                             "v_alignbit_b32 %[u3], %[cin], %[u3], 1\n\t"
-                             "v_or_b32 %[p0], %[u0], %[x0]\n\t"
-                             "v_or_b32 %[p1], %[u1], %[x1]\n\t"
-                             "v_or_b32 %[p2], %[u2], %[x2]\n\t"
-                             "v_or_b32 %[p3], %[u3], %[x3]"
+                uint32_t n0, n1, n2, n3;
+                asm volatile("v_alignbit_b32 %[n0], %[x1], %[x0], 1\n\t"
+                             "v_alignbit_b32 %[n1], %[x2], %[x1], 1\n\t"
+                             "v_alignbit_b32 %[n2], %[x3], %[x2], 1\n\t"
+                             "v_alignbit_b32 %[n3], %[cin], %[x3], 1\n\t"
+                             "v_or3_b32 %[p0], %[s0], %[n0], %[x0]\n\t"
+                             "v_or3_b32 %[p1], %[s1], %[n1], %[x1]\n\t"
+                             "v_or3_b32 %[p2], %[s2], %[n2], %[x2]\n\t"
+                             "v_or3_b32 %[p3], %[s3], %[n3], %[x3]"
                              : [p0] "+v"(A[0][t]), [p1] "+v"(A[1][t]), [p2] "+v"(A[2][t]), [p3] "+v"(A[3][t]),
-                               [u0] "=&v"(u0), [u1] "=&v"(u1), [u2] "=&v"(u2), [u3] "=&v"(u3)
-                             : [x0] "v"(x0), [x1] "v"(x1), [x2] "v"(x2), [x3] "v"(x3), [cin] "v"(cin));
+                               [n0] "=&v"(n0), [n1] "=&v"(n1), [n2] "=&v"(n2), [n3] "=&v"(n3)
+                             : [x0] "v"(x0), [x1] "v"(x1), [x2] "v"(x2), [x3] "v"(x3), [s0] "v"(s0), [s1] "v"(s1),
+                               [s2] "v"(s2), [s3] "v"(s3), [cin] "v"(cin));
+                s0 = n0;
+                s1 = n1;
+                s2 = n2;
+                s3 = n3;
             }
             // M term from row d of the right neighbour, descending columns
 #pragma unroll
@@ -297,7 +311,7 @@ __global__ __launch_bounds__(64, NG == 4 ? 3 : 2) void wide_kernel(const AlignAr
             }
             // keep the row for traceback
             if (computing && storer && dl >= 0 && dl < kRowsW) {
-                uint4* row = gdent + (size_t)dl * stride + CB * q;
+                uint4* row = reinterpret_cast<uint4*>(bdent + (qbyte + __umul24((uint32_t)dl, rowbytes)));
 #pragma unroll
                 for (int t = 0; t < CB; ++t) row[t] = uint4{A[0][t], A[1][t], A[2][t], A[3][t]};
             }
@@ -346,27 +360,33 @@ __global__ __launch_bounds__(64, NG == 4 ? 3 : 2) void wide_kernel(const AlignAr
             const bool tracing = slot && gst == W_TB;
             const GroupRecW r = grec[g];
             const int jlim = min(mw, cap);
+            const int ilim = min(nw, cap);              // a match run stops at the text window's end and at the cap
+            uint32_t* const rout = a.runs + roff;       // the pair's run list (m + n + 1 >= 1 entries)
+            const int rlast = (int)rcap - 1;
             bool fin = !tracing;
             for (int ev = 0; ev < kTbEventsW && __ballot(!fin) != 0; ++ev) {
                 if (!fin) {
-                    // match run at (ti, tj); characters past n_w never match
+                    // match run at (tb_i, tb_j); characters past n_w never match
                     const V128 ta = shr128(r.tlo, tb_i), tb = shr128(r.thi, tb_i);
                     const V128 pa = shr128(r.plo, tb_j), pb = shr128(r.phi, tb_j);
                     const V128 x{(ta.lo ^ pa.lo) | (tb.lo ^ pb.lo), (ta.hi ^ pa.hi) | (tb.hi ^ pb.hi)};
-                    int L0 = ctz128(x);
-                    L0 = min(L0, min(nw - tb_i, min(jlim - tb_j, cap - tb_i)));
-                    L0 = max(L0, 0);
-                    emit_run(0, L0, cur_op, cur_len, nruns, a.runs, roff, rcap);
-                    tb_i += L0;
-                    tb_j += L0;
-                    fin = tb_j >= jlim || tb_i >= cap;
-                }
-                if (!fin) {
-                    // edit step: bits tj, tj+1 of row td-1 at columns ti and ti+1
-                    const int ti = tb_i, tj = tb_j, td = tb_d;
-                    const uint4* rowp = gdent + (size_t)(max(td, 1) - 1) * stride;
-                    const uint4 e0 = rowp[min(ti, stride - 1)];
-                    const uint4 e1 = rowp[min(ti + 1, stride - 1)];
+                    const int L0 = max(min(ctz128(x), min(ilim - tb_i, jlim - tb_j)), 0);
+                    const int ti = tb_i + L0, tj = tb_j + L0, td = tb_d;
+                    // edit step at (ti, tj, td): bits tj, tj+1 of row td-1 at columns ti and ti+1.
+                    // The loads go out first; the run bookkeeping below overlaps them.
+                    const uint32_t ro = gbyte + __umul24((uint32_t)(max(td, 1) - 1), rowbytes);
+                    const uint4 e0 = *reinterpret_cast<const uint4*>(bdent + (ro + (uint32_t)min(ti, stride - 1) * 16u));
+                    const uint4 e1 = *reinterpret_cast<const uint4*>(bdent + (ro + (uint32_t)min(ti + 1, stride - 1) * 16u));
+                    // the run list always holds the open run at index nruns, so
+                    // extending or starting a run is one unconditional store
+                    {
+                        const bool same = cur_op == 0;
+                        nruns += (!same && cur_len > 0 && L0 > 0) ? 1 : 0;
+                        cur_len = L0 == 0 ? cur_len : (same ? cur_len + L0 : L0);
+                        cur_op = L0 == 0 ? cur_op : 0;
+                        rout[min(nruns, rlast)] = ((uint32_t)cur_len << 2) | (uint32_t)cur_op;
+                    }
+                    const bool edit = !(tj >= jlim || ti >= cap);
                     const V128 rc = z_init128(mw, td - 1);
                     const V128 v0{(uint64_t)e0.x | ((uint64_t)e0.y << 32), (uint64_t)e0.z | ((uint64_t)e0.w << 32)};
                     const V128 v1{(uint64_t)e1.x | ((uint64_t)e1.y << 32), (uint64_t)e1.z | ((uint64_t)e1.w << 32)};
@@ -376,14 +396,20 @@ __global__ __launch_bounds__(64, NG == 4 ? 3 : 2) void wide_kernel(const AlignAr
                     const int sb = has_t & zbit128(zb, tj + 1);
                     const int ib = zbit128(za, tj + 1);
                     const int db = has_t & zbit128(zb, tj);
-                    tb_bad |= (td <= 0) | !(sb | ib | db);
                     const int op = sb ? 1 : (ib ? 2 : 3);
-                    tb_i += op != 2;
-                    tb_j += op != 3;
-                    tb_d -= 1;
-                    tb_e += 1;
-                    emit_run(op, 1, cur_op, cur_len, nruns, a.runs, roff, rcap);
-                    fin = tb_j >= jlim || tb_i >= cap || tb_bad;
+                    tb_bad |= edit & ((td <= 0) | !(sb | ib | db));
+                    tb_i = ti + (edit && op != 2 ? 1 : 0);
+                    tb_j = tj + (edit && op != 3 ? 1 : 0);
+                    tb_d = td - (edit ? 1 : 0);
+                    tb_e += edit ? 1 : 0;
+                    {
+                        const bool same = cur_op == op;
+                        nruns += (edit && !same && cur_len > 0) ? 1 : 0;
+                        cur_len = !edit ? cur_len : (same ? cur_len + 1 : 1);
+                        cur_op = !edit ? cur_op : op;
+                        rout[min(nruns, rlast)] = ((uint32_t)cur_len << 2) | (uint32_t)cur_op;
+                    }
+                    fin = !edit || tb_j >= jlim || tb_i >= cap || tb_bad;
                 }
             }
             if (tracing && fin) {
@@ -392,10 +418,7 @@ __global__ __launch_bounds__(64, NG == 4 ? 3 : 2) void wide_kernel(const AlignAr
                 t0 += tb_i;
                 gst = W_EMPTY;
                 if (tb_bad || p0 >= m) {
-                    if (cur_len > 0) {
-                        if (nruns < rcap) a.runs[roff + nruns] = ((uint32_t)cur_len << 2) | (uint32_t)cur_op;
-                        ++nruns;
-                    }
+                    nruns += cur_len > 0 ? 1 : 0;   // the open run is already in the list
                     const bool ok = !tb_bad && nruns <= rcap;
                     if (!ok) c_err += 1;
                     a.edits[pair] = ok ? edits : -1;

@@ -42,42 +42,36 @@ struct RowRegs {
 // Row d of columns CB*q+CB-1 .. CB*q, in place over row d-1.  (nl, nh) is row d
 // and (sl, sh) row d-1 of column CB*q+CB; tm and cin are the bits shifted in
 // by the M term and by the I/S terms.  The I, S and D terms need only row
-// d-1, so a first pass (ascending columns, each column still finds its right
-// neighbour's old value) leaves ((Z[t] | Z[t+1]) >> 1 | cin) | Z[t+1] in place;
-// the M term needs row d of the right neighbour, so a second pass runs from
-// column CB*q+CB-1 down and ORs it in.
+// d-1: with S[t] = Z[t] >> 1 | cin they are S[t] | S[t+1] | Z[t+1], and
+// S[t+1] serves columns t and t+1, so a first pass shifts every column once
+// and then ORs three terms per word in ascending order (each column still
+// finds its right neighbour's old value).  The M term needs row d of the right
+// neighbour, so a second pass runs from column CB*q+CB-1 down and ORs it in.
 template <int CB>
 __device__ __forceinline__ void dc_row(RowRegs<CB>& P, const RowRegs<CB>& eq, uint32_t nl, uint32_t nh, uint32_t sl,
                                        uint32_t sh, uint32_t tm, uint32_t cin) {
-    // first pass as register-tied assembly, in three sweeps over the columns
-    // so that no instruction waits on the one just before it: U = Z[t] |
-    // Z[t+1]; U = U >> 1 | cin; Z[t] = U | Z[t+1] (ascending, so Z[t+1] is
-    // still row d-1).  Left to itself the compiler rotates the whole row
-    // through new registers and copies it back every step.
-    uint32_t ul[CB], uh[CB];
+    // first pass as register-tied assembly: all shifts, then all ORs, so that
+    // no instruction waits on the one just before it.  Left to itself the
+    // compiler rotates the whole row through new registers every step.
+    uint32_t ul[CB + 1], uh[CB + 1];
 #pragma unroll
-    for (int t = 0; t < CB; ++t) {
-        const uint32_t xl = t < CB - 1 ? P.lo[t + 1] : sl;
-        const uint32_t xh = t < CB - 1 ? P.hi[t + 1] : sh;
-        asm volatile("v_or_b32 %[ul], %[pl], %[xl]\n\t"
-                     "v_or_b32 %[uh], %[ph], %[xh]"
+    for (int t = 0; t <= CB; ++t) {
+        const uint32_t zl = t < CB ? P.lo[t] : sl;
+        const uint32_t zh = t < CB ? P.hi[t] : sh;
+        asm volatile("v_alignbit_b32 %[ul], %[zh], %[zl], 1\n\t"
+                     "v_alignbit_b32 %[uh], %[cin], %[zh], 1"
                      : [ul] "=&v"(ul[t]), [uh] "=&v"(uh[t])
-                     : [pl] "v"(P.lo[t]), [ph] "v"(P.hi[t]), [xl] "v"(xl), [xh] "v"(xh));
+                     : [zl] "v"(zl), [zh] "v"(zh), [cin] "v"(cin));
     }
 #pragma unroll
-    for (int t = 0; t < CB; ++t)
-        asm volatile("v_alignbit_b32 %[ul], %[uh], %[ul], 1\n\t"
-                     "v_alignbit_b32 %[uh], %[cin], %[uh], 1"
-                     : [ul] "+v"(ul[t]), [uh] "+v"(uh[t])
-                     : [cin] "v"(cin));
-#pragma unroll
     for (int t = 0; t < CB; ++t) {
         const uint32_t xl = t < CB - 1 ? P.lo[t + 1] : sl;
         const uint32_t xh = t < CB - 1 ? P.hi[t + 1] : sh;
-        asm volatile("v_or_b32 %[pl], %[ul], %[xl]\n\t"
-                     "v_or_b32 %[ph], %[uh], %[xh]"
+        asm volatile("v_or3_b32 %[pl], %[ul0], %[ul1], %[xl]\n\t"
+                     "v_or3_b32 %[ph], %[uh0], %[uh1], %[xh]"
                      : [pl] "+v"(P.lo[t]), [ph] "+v"(P.hi[t])
-                     : [ul] "v"(ul[t]), [uh] "v"(uh[t]), [xl] "v"(xl), [xh] "v"(xh));
+                     : [ul0] "v"(ul[t]), [ul1] "v"(ul[t + 1]), [uh0] "v"(uh[t]), [uh1] "v"(uh[t + 1]), [xl] "v"(xl),
+                       [xh] "v"(xh));
     }
     // second pass, also register-tied: ((right neighbour's row d) >> 1 | tm) & EQ
 #pragma unroll
