@@ -272,9 +272,12 @@ __global__ __launch_bounds__(64) void cols_kernel(const AlignArgs a) {
 
         // ---- 5. DC pass: one row of every running window per step ----
         int steps = 0;
+        // the lane's row at which column 0 reaches the window's last row / its budget
+        const int dstop = full - 1 + q, dover = limit - 1 + q;
+        const int et = a.no_et ? 0 : 1;
         if (any_run) do {
             // every lane computes; only lanes of running windows store and count
-            const bool computing = gst == G_RUN || gst == G_OVER;
+            const int computing = gst & 1;   // G_RUN or G_OVER
             const uint32_t tm = dl >= 0 ? 1u : 0u;    // the M term shifts in a 1 from the lane's first row on
             const uint32_t cin = dl >= 1 ? 1u : 0u;   // the I/S terms from its second row on
             uint32_t nlo = from_upper_lane(A.lo[0]);
@@ -293,7 +296,7 @@ __global__ __launch_bounds__(64) void cols_kernel(const AlignArgs a) {
                 zrhi = zh;
             }
             // keep the row for traceback
-            if (computing && storer && dl >= 0 && dl < kStoredRows) {
+            if (computing && storer && (uint32_t)dl < (uint32_t)kStoredRows) {
                 uint4* row = reinterpret_cast<uint4*>(bdent + (qbyte + __umul24((uint32_t)dl, rowbytes)));
                 if (NARROW) {
 #pragma unroll
@@ -303,16 +306,18 @@ __global__ __launch_bounds__(64) void cols_kernel(const AlignArgs a) {
                     for (int t = 0; t < CB; t += 2) row[t >> 1] = uint4{A.lo[t], A.hi[t], A.lo[t + 1], A.hi[t + 1]};
                 }
             }
-            // early termination: column 0 of row d has the msb of R clear
-            const uint64_t hb = __ballot(slot && computing && dl >= 0 && (A.lo[0] & 1u));
+            // early termination: column 0 of row d has the msb of R clear.  Lane 0 of
+            // a group holds column 0; a lane's rows stay zero until its first row, so
+            // the ballot needs no row test, and each lane reads its slot lane's bit.
+            const uint64_t hb = __ballot(A.lo[0] & 1u);
             {   // state update without branches
-                const int d0 = dl - q;   // row of column 0 computed at this step
-                const bool hit = computing && (hb & gbit) != 0 && dw < 0;   // first row with a hit
-                const bool done = (hit && !a.no_et) || (computing && d0 >= full - 1);   // no hit: dw stays -1
-                const bool over = !done && gst == G_RUN && d0 >= limit - 1;   // over budget: no longer waited for
-                dw = hit ? d0 : dw;
+                const int hbit = (int)(hb >> (lane - q)) & 1;
+                const int hit = computing & hbit & (dw < 0 ? 1 : 0);              // first row with a hit
+                const int done = (hit & et) | (computing & (dl >= dstop ? 1 : 0));  // no hit: dw stays -1
+                const int over = (done ^ 1) & (gst == G_RUN ? 1 : 0) & (dl >= dover ? 1 : 0);   // over budget
+                dw = hit ? dl - q : dw;
                 gst = done ? G_DONE : (over ? G_OVER : gst);
-                over_events += over ? 1 : 0;
+                over_events += over;
             }
             dl += 1;
             steps += 1;

@@ -247,8 +247,32 @@ __global__ __launch_bounds__(64, NG == 4 ? 3 : 2) void wide_kernel(const AlignAr
             }
             // I, S and D terms from row d-1: with S[t] = Z[t] >> 1 | cin they are
             // S[t] | S[t+1] | Z[t+1].  Ascending columns (each column still sees its
-            // right neighbour's row d-1), S[t+1] carried to the next column; register-tied
-            uint32_t s0, s1, s2, s3;
+            // right neighbour's row d-1), S[t+1] carried to the next column; then the
+            // M term from row d of the right neighbour, descending columns.  Both are
+            // register-tied, four columns per statement: the compiler separates
+            // consecutive statements that share registers by a wait state.
+#define SCG_W1COL(T, X0, X1, X2, X3, S, N)                                          \
+    "v_alignbit_b32 %[" N "0], %[" X1 "], %[" X0 "], 1\n\t"                         \
+    "v_alignbit_b32 %[" N "1], %[" X2 "], %[" X1 "], 1\n\t"                         \
+    "v_alignbit_b32 %[" N "2], %[" X3 "], %[" X2 "], 1\n\t"                         \
+    "v_alignbit_b32 %[" N "3], %[cin], %[" X3 "], 1\n\t"                            \
+    "v_or3_b32 %[a" #T "0], %[" S "0], %[" N "0], %[" X0 "]\n\t"                    \
+    "v_or3_b32 %[a" #T "1], %[" S "1], %[" N "1], %[" X1 "]\n\t"                    \
+    "v_or3_b32 %[a" #T "2], %[" S "2], %[" N "2], %[" X2 "]\n\t"                    \
+    "v_or3_b32 %[a" #T "3], %[" S "3], %[" N "3], %[" X3 "]\n\t"
+#define SCG_W2COL(T, N0, N1, N2, N3)                                                \
+    "v_alignbit_b32 %[b3], %[tm], %[" N3 "], 1\n\t"                                 \
+    "v_alignbit_b32 %[b2], %[" N3 "], %[" N2 "], 1\n\t"                             \
+    "v_alignbit_b32 %[b1], %[" N2 "], %[" N1 "], 1\n\t"                             \
+    "v_alignbit_b32 %[b0], %[" N1 "], %[" N0 "], 1\n\t"                             \
+    "v_and_or_b32 %[a" #T "3], %[b3], %[e" #T "3], %[a" #T "3]\n\t"                 \
+    "v_and_or_b32 %[a" #T "2], %[b2], %[e" #T "2], %[a" #T "2]\n\t"                 \
+    "v_and_or_b32 %[a" #T "1], %[b1], %[e" #T "1], %[a" #T "1]\n\t"                 \
+    "v_and_or_b32 %[a" #T "0], %[b0], %[e" #T "0], %[a" #T "0]\n\t"
+#define SCG_WA(T, U) [a##T##0] "+v"(A[0][U]), [a##T##1] "+v"(A[1][U]), [a##T##2] "+v"(A[2][U]), [a##T##3] "+v"(A[3][U])
+#define SCG_WE(T, U) [e##T##0] "v"(E[0][U]), [e##T##1] "v"(E[1][U]), [e##T##2] "v"(E[2][U]), [e##T##3] "v"(E[3][U])
+            static_assert(CB % 4 == 0, "columns per lane come in fours");
+            uint32_t s0, s1, s2, s3;   // S[t] of the next column to update
             asm volatile("v_alignbit_b32 %[s0], %[z1], %[z0], 1\n\t"
                          "v_alignbit_b32 %[s1], %[z2], %[z1], 1\n\t"
                          "v_alignbit_b32 %[s2], %[z3], %[z2], 1\n\t"
@@ -256,50 +280,39 @@ __global__ __launch_bounds__(64, NG == 4 ? 3 : 2) void wide_kernel(const AlignAr
                          : [s0] "=&v"(s0), [s1] "=&v"(s1), [s2] "=&v"(s2), [s3] "=&v"(s3)
                          : [z0] "v"(A[0][0]), [z1] "v"(A[1][0]), [z2] "v"(A[2][0]), [z3] "v"(A[3][0]), [cin] "v"(cin));
 #pragma unroll
-            for (int t = 0; t < CB; ++t) {
-                const uint32_t x0 = t < CB - 1 ? A[0][t + 1] : nbs[0];
-                const uint32_t x1 = t < CB - 1 ? A[1][t + 1] : nbs[1];
-                const uint32_t x2 = t < CB - 1 ? A[2][t + 1] : nbs[2];
-                const uint32_t x3 = t < CB - 1 ? A[3][t + 1] : nbs[3];
+            for (int t0 = 0; t0 < CB; t0 += 4) {
+                const uint32_t x0 = t0 + 4 < CB ? A[0][t0 + 4] : nbs[0];
+                const uint32_t x1 = t0 + 4 < CB ? A[1][t0 + 4] : nbs[1];
+                const uint32_t x2 = t0 + 4 < CB ? A[2][t0 + 4] : nbs[2];
+                const uint32_t x3 = t0 + 4 < CB ? A[3][t0 + 4] : nbs[3];
                 uint32_t n0, n1, n2, n3;
-                asm volatile("v_alignbit_b32 %[n0], %[x1], %[x0], 1\n\t"
-                             "v_alignbit_b32 %[n1], %[x2], %[x1], 1\n\t"
-                             "v_alignbit_b32 %[n2], %[x3], %[x2], 1\n\t"
-                             "v_alignbit_b32 %[n3], %[cin], %[x3], 1\n\t"
-                             "v_or3_b32 %[p0], %[s0], %[n0], %[x0]\n\t"
-                             "v_or3_b32 %[p1], %[s1], %[n1], %[x1]\n\t"
-                             "v_or3_b32 %[p2], %[s2], %[n2], %[x2]\n\t"
-                             "v_or3_b32 %[p3], %[s3], %[n3], %[x3]"
-                             : [p0] "+v"(A[0][t]), [p1] "+v"(A[1][t]), [p2] "+v"(A[2][t]), [p3] "+v"(A[3][t]),
+                asm volatile(SCG_W1COL(0, "a10", "a11", "a12", "a13", "s", "n")
+                             SCG_W1COL(1, "a20", "a21", "a22", "a23", "n", "s")
+                             SCG_W1COL(2, "a30", "a31", "a32", "a33", "s", "n")
+                             SCG_W1COL(3, "x0", "x1", "x2", "x3", "n", "s")
+                             : SCG_WA(0, t0), SCG_WA(1, t0 + 1), SCG_WA(2, t0 + 2), SCG_WA(3, t0 + 3),
+                               [s0] "+v"(s0), [s1] "+v"(s1), [s2] "+v"(s2), [s3] "+v"(s3),
                                [n0] "=&v"(n0), [n1] "=&v"(n1), [n2] "=&v"(n2), [n3] "=&v"(n3)
-                             : [x0] "v"(x0), [x1] "v"(x1), [x2] "v"(x2), [x3] "v"(x3), [s0] "v"(s0), [s1] "v"(s1),
-                               [s2] "v"(s2), [s3] "v"(s3), [cin] "v"(cin));
-                s0 = n0;
-                s1 = n1;
-                s2 = n2;
-                s3 = n3;
+                             : [x0] "v"(x0), [x1] "v"(x1), [x2] "v"(x2), [x3] "v"(x3), [cin] "v"(cin));
             }
-            // M term from row d of the right neighbour, descending columns
 #pragma unroll
-            for (int t = CB - 1; t >= 0; --t) {
-                const uint32_t n0 = t < CB - 1 ? A[0][t + 1] : nb[0];
-                const uint32_t n1 = t < CB - 1 ? A[1][t + 1] : nb[1];
-                const uint32_t n2 = t < CB - 1 ? A[2][t + 1] : nb[2];
-                const uint32_t n3 = t < CB - 1 ? A[3][t + 1] : nb[3];
+            for (int t0 = CB - 4; t0 >= 0; t0 -= 4) {
+                const uint32_t y0 = t0 + 4 < CB ? A[0][t0 + 4] : nb[0];
+                const uint32_t y1 = t0 + 4 < CB ? A[1][t0 + 4] : nb[1];
+                const uint32_t y2 = t0 + 4 < CB ? A[2][t0 + 4] : nb[2];
+                const uint32_t y3 = t0 + 4 < CB ? A[3][t0 + 4] : nb[3];
                 uint32_t b0, b1, b2, b3;
-                asm volatile("v_alignbit_b32 %[b3], %[tm], %[n3], 1\n\t"
-                             "v_alignbit_b32 %[b2], %[n3], %[n2], 1\n\t"
-                             "v_alignbit_b32 %[b1], %[n2], %[n1], 1\n\t"
-                             "v_alignbit_b32 %[b0], %[n1], %[n0], 1\n\t"
-                             "v_and_or_b32 %[p3], %[b3], %[e3], %[p3]\n\t"
-                             "v_and_or_b32 %[p2], %[b2], %[e2], %[p2]\n\t"
-                             "v_and_or_b32 %[p1], %[b1], %[e1], %[p1]\n\t"
-                             "v_and_or_b32 %[p0], %[b0], %[e0], %[p0]"
-                             : [p0] "+v"(A[0][t]), [p1] "+v"(A[1][t]), [p2] "+v"(A[2][t]), [p3] "+v"(A[3][t]),
+                asm volatile(SCG_W2COL(3, "y0", "y1", "y2", "y3") SCG_W2COL(2, "a30", "a31", "a32", "a33")
+                             SCG_W2COL(1, "a20", "a21", "a22", "a23") SCG_W2COL(0, "a10", "a11", "a12", "a13")
+                             : SCG_WA(0, t0), SCG_WA(1, t0 + 1), SCG_WA(2, t0 + 2), SCG_WA(3, t0 + 3),
                                [b0] "=&v"(b0), [b1] "=&v"(b1), [b2] "=&v"(b2), [b3] "=&v"(b3)
-                             : [n0] "v"(n0), [n1] "v"(n1), [n2] "v"(n2), [n3] "v"(n3), [tm] "v"(tm),
-                               [e0] "v"(E[0][t]), [e1] "v"(E[1][t]), [e2] "v"(E[2][t]), [e3] "v"(E[3][t]));
+                             : [y0] "v"(y0), [y1] "v"(y1), [y2] "v"(y2), [y3] "v"(y3), [tm] "v"(tm),
+                               SCG_WE(0, t0), SCG_WE(1, t0 + 1), SCG_WE(2, t0 + 2), SCG_WE(3, t0 + 3));
             }
+#undef SCG_WE
+#undef SCG_WA
+#undef SCG_W2COL
+#undef SCG_W1COL
 #pragma unroll
             for (int k = 0; k < 4; ++k) nbs[k] = nb[k];
             {   // initial column, one row further: z >> 1 with a 1 shifted in at the top

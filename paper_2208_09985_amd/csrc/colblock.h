@@ -73,21 +73,52 @@ __device__ __forceinline__ void dc_row(RowRegs<CB>& P, const RowRegs<CB>& eq, ui
                      : [ul0] "v"(ul[t]), [ul1] "v"(ul[t + 1]), [uh0] "v"(uh[t]), [uh1] "v"(uh[t + 1]), [xl] "v"(xl),
                        [xh] "v"(xh));
     }
-    // second pass, also register-tied: ((right neighbour's row d) >> 1 | tm) & EQ
+    // second pass, also register-tied: ((right neighbour's row d) >> 1 | tm) & EQ,
+    // eight (or four) columns per assembly statement: the compiler separates
+    // consecutive statements that share registers by a wait state, as it cannot
+    // see inside them.  High half first: each column's first instruction then
+    // reads a result two instructions old.
+#define SCG_MCOL(T, XH, XL)                                              \
+    "v_alignbit_b32 %[bh], %[tm], %[" XH "], 1\n\t"                     \
+    "v_alignbit_b32 %[bl], %[" XH "], %[" XL "], 1\n\t"                 \
+    "v_and_or_b32 %[ph" #T "], %[bh], %[eh" #T "], %[ph" #T "]\n\t"     \
+    "v_and_or_b32 %[pl" #T "], %[bl], %[el" #T "], %[pl" #T "]\n\t"
+#define SCG_MOUT(T, U) [pl##T] "+v"(P.lo[U]), [ph##T] "+v"(P.hi[U])
+#define SCG_MIN(T, U) [el##T] "v"(eq.lo[U]), [eh##T] "v"(eq.hi[U])
+    if constexpr (CB % 8 == 0) {
 #pragma unroll
-    for (int t = CB - 1; t >= 0; --t) {
-        const uint32_t xl = t < CB - 1 ? P.lo[t + 1] : nl;
-        const uint32_t xh = t < CB - 1 ? P.hi[t + 1] : nh;
-        uint32_t bl, bh;
-        // high half first: the next column's first instruction then reads
-        // a result two instructions old
-        asm volatile("v_alignbit_b32 %[bh], %[tm], %[xh], 1\n\t"
-                     "v_alignbit_b32 %[bl], %[xh], %[xl], 1\n\t"
-                     "v_and_or_b32 %[ph], %[bh], %[eh], %[ph]\n\t"
-                     "v_and_or_b32 %[pl], %[bl], %[el], %[pl]"
-                     : [pl] "+v"(P.lo[t]), [ph] "+v"(P.hi[t]), [bl] "=&v"(bl), [bh] "=&v"(bh)
-                     : [xl] "v"(xl), [xh] "v"(xh), [tm] "v"(tm), [el] "v"(eq.lo[t]), [eh] "v"(eq.hi[t]));
+        for (int t0 = CB - 8; t0 >= 0; t0 -= 8) {
+            const uint32_t xl = t0 + 8 < CB ? P.lo[t0 + 8] : nl;
+            const uint32_t xh = t0 + 8 < CB ? P.hi[t0 + 8] : nh;
+            uint32_t bl, bh;
+            asm volatile(SCG_MCOL(7, "xh", "xl") SCG_MCOL(6, "ph7", "pl7") SCG_MCOL(5, "ph6", "pl6")
+                         SCG_MCOL(4, "ph5", "pl5") SCG_MCOL(3, "ph4", "pl4") SCG_MCOL(2, "ph3", "pl3")
+                         SCG_MCOL(1, "ph2", "pl2") SCG_MCOL(0, "ph1", "pl1")
+                         : SCG_MOUT(0, t0), SCG_MOUT(1, t0 + 1), SCG_MOUT(2, t0 + 2), SCG_MOUT(3, t0 + 3),
+                           SCG_MOUT(4, t0 + 4), SCG_MOUT(5, t0 + 5), SCG_MOUT(6, t0 + 6), SCG_MOUT(7, t0 + 7),
+                           [bl] "=&v"(bl), [bh] "=&v"(bh)
+                         : [xl] "v"(xl), [xh] "v"(xh), [tm] "v"(tm), SCG_MIN(0, t0), SCG_MIN(1, t0 + 1),
+                           SCG_MIN(2, t0 + 2), SCG_MIN(3, t0 + 3), SCG_MIN(4, t0 + 4), SCG_MIN(5, t0 + 5),
+                           SCG_MIN(6, t0 + 6), SCG_MIN(7, t0 + 7));
+        }
+    } else {
+        static_assert(CB % 4 == 0, "columns per lane come in fours");
+#pragma unroll
+        for (int t0 = CB - 4; t0 >= 0; t0 -= 4) {
+            const uint32_t xl = t0 + 4 < CB ? P.lo[t0 + 4] : nl;
+            const uint32_t xh = t0 + 4 < CB ? P.hi[t0 + 4] : nh;
+            uint32_t bl, bh;
+            asm volatile(SCG_MCOL(3, "xh", "xl") SCG_MCOL(2, "ph3", "pl3") SCG_MCOL(1, "ph2", "pl2")
+                         SCG_MCOL(0, "ph1", "pl1")
+                         : SCG_MOUT(0, t0), SCG_MOUT(1, t0 + 1), SCG_MOUT(2, t0 + 2), SCG_MOUT(3, t0 + 3),
+                           [bl] "=&v"(bl), [bh] "=&v"(bh)
+                         : [xl] "v"(xl), [xh] "v"(xh), [tm] "v"(tm), SCG_MIN(0, t0), SCG_MIN(1, t0 + 1),
+                           SCG_MIN(2, t0 + 2), SCG_MIN(3, t0 + 3));
+        }
     }
+#undef SCG_MIN
+#undef SCG_MOUT
+#undef SCG_MCOL
 }
 
 }  // namespace colblock
