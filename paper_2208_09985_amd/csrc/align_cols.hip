@@ -110,6 +110,7 @@ __global__ __launch_bounds__(64) void cols_kernel(const AlignArgs a) {
     bool exhausted = !slot;
     unsigned long long c_windows = 0, c_ops = 0, c_fallback = 0, c_rows = 0, c_err = 0, c_yield = 0;
     int tb_i = 0, tb_j = 0, tb_d = 0, tb_e = 0, tb_bad = 0;   // slot lane: traceback position and edits
+    uint64_t tb_rc = 0;   // slot lane: the initial column at row tb_d - 1 (Z beyond the text window)
 
     unsigned long long c_lane_steps = 0, c_rounds = 0;
 
@@ -353,6 +354,7 @@ __global__ __launch_bounds__(64) void cols_kernel(const AlignArgs a) {
                 c_windows += 1;
                 c_ops += (unsigned long long)(tb_d + 1) + 2ull * nw + 7ull * nw * tb_d;
                 tb_i = tb_j = tb_e = tb_bad = 0;
+                tb_rc = z_init(mw, tb_d - 1);
             }
         }
         if (gst == G_DONE) gst = G_TB;
@@ -363,9 +365,13 @@ __global__ __launch_bounds__(64) void cols_kernel(const AlignArgs a) {
             const int ilim = min(nw, cap);              // a match run stops at the text window's end and at the cap
             uint32_t* const rout = a.runs + roff;       // the pair's run list (m + n + 1 >= 1 entries)
             const int rlast = (int)rcap - 1;
-            bool fin = !tracing;
-            for (int ev = 0; ev < kTbEvents && __ballot(!fin) != 0; ++ev) {
-                if (!fin) {
+            // `fin` is an integer so that it lives in a vector register: a boolean
+            // carried around a loop with a divergent body is kept as a lane mask
+            // that the compiler re-merges with scalar operations at every event
+            int fin = tracing ? 0 : 1;
+            for (int ev = 0; ev < kTbEvents; ++ev) {
+                if (__ballot(fin == 0) == 0) break;
+                if (fin == 0) {
                     // match run at (tb_i, tb_j); characters past n_w never match
                     const uint64_t x = ((r.thi >> tb_i) ^ (r.phi >> tb_j)) | ((r.tlo >> tb_i) ^ (r.plo >> tb_j));
                     int L = x ? (int)__builtin_ctzll(x) : 64;
@@ -391,30 +397,33 @@ __global__ __launch_bounds__(64) void cols_kernel(const AlignArgs a) {
                         nruns += (!same && cur_len > 0 && L > 0) ? 1 : 0;
                         cur_len = L == 0 ? cur_len : (same ? cur_len + L : L);
                         cur_op = L == 0 ? cur_op : 0;
-                        rout[min(nruns, rlast)] = ((uint32_t)cur_len << 2) | (uint32_t)cur_op;
+                        rout[(uint32_t)min(nruns, rlast)] = ((uint32_t)cur_len << 2) | (uint32_t)cur_op;
                     }
                     const bool edit = !(tj >= jlim || ti >= cap);
-                    const uint64_t rc = z_init(mw, td - 1);
-                    const uint64_t za = ti < nw ? v0 : rc;        // Z[ti][td-1]
-                    const uint64_t zb = ti + 1 < nw ? v1 : rc;    // Z[ti+1][td-1]
+                    const uint64_t za = ti < nw ? v0 : tb_rc;        // Z[ti][td-1]
+                    const uint64_t zb = ti + 1 < nw ? v1 : tb_rc;    // Z[ti+1][td-1]
                     const int has_t = ti < nw;
-                    const int sb = has_t & zbit(zb, tj + 1);
-                    const int ib = zbit(za, tj + 1);
-                    const int db = has_t & zbit(zb, tj);
+                    // bits tj and tj+1 (tj <= 63 in an edit step; bit 64 is the implicit set bit)
+                    const uint64_t sa = za >> (tj & 63), sz = zb >> (tj & 63);
+                    const int top = tj >= 63 ? 1 : 0;
+                    const int sb = has_t & (((int)(sz >> 1) & 1) | top);
+                    const int ib = ((int)(sa >> 1) & 1) | top;
+                    const int db = has_t & (int)(sz & 1);
                     const int op = sb ? 1 : (ib ? 2 : 3);
                     tb_bad |= edit & ((td <= 0) | !(sb | ib | db));
                     tb_i = ti + (edit && op != 2 ? 1 : 0);
                     tb_j = tj + (edit && op != 3 ? 1 : 0);
                     tb_d = td - (edit ? 1 : 0);
                     tb_e += edit ? 1 : 0;
+                    tb_rc = edit ? tb_rc << 1 : tb_rc;   // one row down: m_w - d grows by one (it is >= 1 here)
                     {
                         const bool same = cur_op == op;
                         nruns += (edit && !same && cur_len > 0) ? 1 : 0;
                         cur_len = !edit ? cur_len : (same ? cur_len + 1 : 1);
                         cur_op = !edit ? cur_op : op;
-                        rout[min(nruns, rlast)] = ((uint32_t)cur_len << 2) | (uint32_t)cur_op;
+                        rout[(uint32_t)min(nruns, rlast)] = ((uint32_t)cur_len << 2) | (uint32_t)cur_op;
                     }
-                    fin = !edit || tb_j >= jlim || tb_i >= cap || tb_bad;
+                    fin = (!edit || tb_j >= jlim || tb_i >= cap || tb_bad) ? 1 : 0;
                 }
             }
             if (tracing && fin) {

@@ -112,6 +112,7 @@ __global__ __launch_bounds__(64, NG == 4 ? 3 : 2) void wide_kernel(const AlignAr
     int64_t roff = 0, rcap = 0, pending = -1;
     bool exhausted = !slot;
     unsigned long long c_windows = 0, c_ops = 0, c_rows = 0, c_err = 0;
+    V128 tb_rc{0ull, 0ull};   // slot lane: the initial column at row tb_d - 1 (Z beyond the text window)
     int tb_i = 0, tb_j = 0, tb_d = 0, tb_e = 0, tb_bad = 0;
     unsigned long long c_lane_steps = 0, c_rounds = 0;
 
@@ -366,6 +367,7 @@ __global__ __launch_bounds__(64, NG == 4 ? 3 : 2) void wide_kernel(const AlignAr
                 c_windows += 1;
                 c_ops += 2ull * ((unsigned long long)(tb_d + 1) + 2ull * nw + 7ull * nw * tb_d);
                 tb_i = tb_j = tb_e = tb_bad = 0;
+                tb_rc = z_init128(mw, tb_d - 1);
             }
         }
         if (gst == W_DONE) gst = W_TB;
@@ -376,9 +378,13 @@ __global__ __launch_bounds__(64, NG == 4 ? 3 : 2) void wide_kernel(const AlignAr
             const int ilim = min(nw, cap);              // a match run stops at the text window's end and at the cap
             uint32_t* const rout = a.runs + roff;       // the pair's run list (m + n + 1 >= 1 entries)
             const int rlast = (int)rcap - 1;
-            bool fin = !tracing;
-            for (int ev = 0; ev < kTbEventsW && __ballot(!fin) != 0; ++ev) {
-                if (!fin) {
+            // `fin` is an integer so that it lives in a vector register: a boolean
+            // carried around a loop with a divergent body is kept as a lane mask
+            // that the compiler re-merges with scalar operations at every event
+            int fin = tracing ? 0 : 1;
+            for (int ev = 0; ev < kTbEventsW; ++ev) {
+                if (__ballot(fin == 0) == 0) break;
+                if (fin == 0) {
                     // match run at (tb_i, tb_j); characters past n_w never match
                     const V128 ta = shr128(r.tlo, tb_i), tb = shr128(r.thi, tb_i);
                     const V128 pa = shr128(r.plo, tb_j), pb = shr128(r.phi, tb_j);
@@ -400,11 +406,10 @@ __global__ __launch_bounds__(64, NG == 4 ? 3 : 2) void wide_kernel(const AlignAr
                         rout[min(nruns, rlast)] = ((uint32_t)cur_len << 2) | (uint32_t)cur_op;
                     }
                     const bool edit = !(tj >= jlim || ti >= cap);
-                    const V128 rc = z_init128(mw, td - 1);
                     const V128 v0{(uint64_t)e0.x | ((uint64_t)e0.y << 32), (uint64_t)e0.z | ((uint64_t)e0.w << 32)};
                     const V128 v1{(uint64_t)e1.x | ((uint64_t)e1.y << 32), (uint64_t)e1.z | ((uint64_t)e1.w << 32)};
-                    const V128 za = ti < nw ? v0 : rc;        // Z[ti][td-1]
-                    const V128 zb = ti + 1 < nw ? v1 : rc;    // Z[ti+1][td-1]
+                    const V128 za = ti < nw ? v0 : tb_rc;        // Z[ti][td-1]
+                    const V128 zb = ti + 1 < nw ? v1 : tb_rc;    // Z[ti+1][td-1]
                     const int has_t = ti < nw;
                     const int sb = has_t & zbit128(zb, tj + 1);
                     const int ib = zbit128(za, tj + 1);
@@ -415,6 +420,7 @@ __global__ __launch_bounds__(64, NG == 4 ? 3 : 2) void wide_kernel(const AlignAr
                     tb_j = tj + (edit && op != 3 ? 1 : 0);
                     tb_d = td - (edit ? 1 : 0);
                     tb_e += edit ? 1 : 0;
+                    if (edit) tb_rc = V128{tb_rc.lo << 1, (tb_rc.hi << 1) | (tb_rc.lo >> 63)};   // m_w - d grows by one
                     {
                         const bool same = cur_op == op;
                         nruns += (edit && !same && cur_len > 0) ? 1 : 0;
@@ -422,7 +428,7 @@ __global__ __launch_bounds__(64, NG == 4 ? 3 : 2) void wide_kernel(const AlignAr
                         cur_op = !edit ? cur_op : op;
                         rout[min(nruns, rlast)] = ((uint32_t)cur_len << 2) | (uint32_t)cur_op;
                     }
-                    fin = !edit || tb_j >= jlim || tb_i >= cap || tb_bad;
+                    fin = (!edit || tb_j >= jlim || tb_i >= cap || tb_bad) ? 1 : 0;
                 }
             }
             if (tracing && fin) {
