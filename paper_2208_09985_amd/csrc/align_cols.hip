@@ -276,52 +276,64 @@ __global__ __launch_bounds__(64) void cols_kernel(const AlignArgs a) {
         // the lane's row at which column 0 reaches the window's last row / its budget
         const int dstop = full - 1 + q, dover = limit - 1 + q;
         const int et = a.no_et ? 0 : 1;
+        uint32_t soff = qbyte + (uint32_t)dl * rowbytes;   // byte offset of the lane's row dl (used once dl >= 0)
         if (any_run) do {
-            // every lane computes; only lanes of running windows store and count
+            // Two steps per iteration, the state update once per two: every lane
+            // computes; only lanes of running windows store and count.  A window
+            // that ends at the first step computes one row more, which nothing reads.
             const int computing = gst & 1;   // G_RUN or G_OVER
-            const uint32_t tm = dl >= 0 ? 1u : 0u;    // the M term shifts in a 1 from the lane's first row on
-            const uint32_t cin = dl >= 1 ? 1u : 0u;   // the I/S terms from its second row on
-            uint32_t nlo = from_upper_lane(A.lo[0]);
-            uint32_t nhi = from_upper_lane(A.hi[0]);
-            if (q == L - 1) {
-                nlo = zrlo;
-                nhi = zrhi;
-            }
-            dc_row(A, E, nlo, nhi, nbslo, nbshi, tm, cin);
-            nbslo = nlo;
-            nbshi = nhi;
-            {   // initial column, one row further
-                const uint32_t zl = __builtin_amdgcn_alignbit(zrhi, zrlo, 1);
-                const uint32_t zh = __builtin_amdgcn_alignbit(1u, zrhi, 1);
-                zrlo = zl;
-                zrhi = zh;
-            }
-            // keep the row for traceback
-            if (computing && storer && (uint32_t)dl < (uint32_t)kStoredRows) {
-                uint4* row = reinterpret_cast<uint4*>(bdent + (qbyte + __umul24((uint32_t)dl, rowbytes)));
-                if (NARROW) {
+            uint64_t hb[2];
 #pragma unroll
-                    for (int t = 0; t < CB; t += 4) row[t >> 2] = uint4{A.lo[t], A.lo[t + 1], A.lo[t + 2], A.lo[t + 3]};
-                } else {
-#pragma unroll
-                    for (int t = 0; t < CB; t += 2) row[t >> 1] = uint4{A.lo[t], A.hi[t], A.lo[t + 1], A.hi[t + 1]};
+            for (int h = 0; h < 2; ++h) {
+                const int dh = dl + h;                    // the row this lane computes at this step
+                const uint32_t tm = dh >= 0 ? 1u : 0u;    // the M term shifts in a 1 from the lane's first row on
+                const uint32_t cin = dh >= 1 ? 1u : 0u;   // the I/S terms from its second row on
+                uint32_t nlo = from_upper_lane(A.lo[0]);
+                uint32_t nhi = from_upper_lane(A.hi[0]);
+                if (q == L - 1) {
+                    nlo = zrlo;
+                    nhi = zrhi;
                 }
+                dc_row(A, E, nlo, nhi, nbslo, nbshi, tm, cin);
+                nbslo = nlo;
+                nbshi = nhi;
+                {   // initial column, one row further
+                    const uint32_t zl = __builtin_amdgcn_alignbit(zrhi, zrlo, 1);
+                    const uint32_t zh = __builtin_amdgcn_alignbit(1u, zrhi, 1);
+                    zrlo = zl;
+                    zrhi = zh;
+                }
+                // keep the row for traceback
+                if (computing && storer && (uint32_t)dh < (uint32_t)kStoredRows) {
+                    uint4* row = reinterpret_cast<uint4*>(bdent + (soff + (h ? rowbytes : 0u)));
+                    if (NARROW) {
+#pragma unroll
+                        for (int t = 0; t < CB; t += 4) row[t >> 2] = uint4{A.lo[t], A.lo[t + 1], A.lo[t + 2], A.lo[t + 3]};
+                    } else {
+#pragma unroll
+                        for (int t = 0; t < CB; t += 2) row[t >> 1] = uint4{A.lo[t], A.hi[t], A.lo[t + 1], A.hi[t + 1]};
+                    }
+                }
+                // early termination: column 0 of row d has the msb of R clear.  Lane 0 of
+                // a group holds column 0; a lane's rows stay zero until its first row, so
+                // the ballot needs no row test, and each lane reads its slot lane's bit.
+                hb[h] = __ballot(A.lo[0] & 1u);
             }
-            // early termination: column 0 of row d has the msb of R clear.  Lane 0 of
-            // a group holds column 0; a lane's rows stay zero until its first row, so
-            // the ballot needs no row test, and each lane reads its slot lane's bit.
-            const uint64_t hb = __ballot(A.lo[0] & 1u);
-            {   // state update without branches
-                const int hbit = (int)(hb >> (lane - q)) & 1;
-                const int hit = computing & hbit & (dw < 0 ? 1 : 0);              // first row with a hit
-                const int done = (hit & et) | (computing & (dl >= dstop ? 1 : 0));  // no hit: dw stays -1
-                const int over = (done ^ 1) & (gst == G_RUN ? 1 : 0) & (dl >= dover ? 1 : 0);   // over budget
-                dw = hit ? dl - q : dw;
+            {   // state update without branches, for rows dl - q and dl + 1 - q of column 0
+                const int b0 = (int)(hb[0] >> (lane - q)) & 1;
+                const int b1 = (int)(hb[1] >> (lane - q)) & 1;
+                const int fresh = computing & (dw < 0 ? 1 : 0);
+                const int hit0 = fresh & b0;                                        // first row with a hit
+                const int hit1 = fresh & (b0 ^ 1) & b1 & (dl + 1 <= dstop ? 1 : 0);  // (not past the last row)
+                const int done = ((hit0 | hit1) & et) | (computing & (dl + 1 >= dstop ? 1 : 0));  // no hit: dw stays -1
+                const int over = (done ^ 1) & (gst == G_RUN ? 1 : 0) & (dl + 1 >= dover ? 1 : 0);   // over budget
+                dw = hit0 ? dl - q : (hit1 ? dl + 1 - q : dw);
                 gst = done ? G_DONE : (over ? G_OVER : gst);
                 over_events += over;
             }
-            dl += 1;
-            steps += 1;
+            dl += 2;
+            soff += 2 * rowbytes;
+            steps += 2;
         } while (__ballot(gst == G_RUN) != 0);
         c_lane_steps += 64ull * (unsigned long long)steps;
         c_rounds += 1;
