@@ -108,10 +108,17 @@ def spec(t):
 
 
 def kernel_source_hash() -> str:
+    """Hash of the measured kernel's sources with comments and blank space
+    removed, so that the counters stay valid across comment-only edits (the
+    sources hold no comment markers inside string literals)."""
+    import re
     h = hashlib.sha256()
     for f in KERNEL_SOURCES:
-        with open(os.path.join(ROOT, "paper_2208_09985_amd", "csrc", f), "rb") as fh:
-            h.update(fh.read())
+        with open(os.path.join(ROOT, "paper_2208_09985_amd", "csrc", f), encoding="utf-8") as fh:
+            text = fh.read()
+        text = re.sub(r"/\*.*?\*/", " ", text, flags=re.S)
+        text = re.sub(r"//[^\n]*", " ", text)
+        h.update(" ".join(text.split()).encode())
     return h.hexdigest()[:16]
 
 

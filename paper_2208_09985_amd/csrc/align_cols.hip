@@ -21,14 +21,16 @@
 //     empty, so windows shorter than 64 need no special case.
 //   * Bitvectors are kept as the complement Z = ~R in LSB-first order (bit j =
 //     pattern position j); the update of Algorithm 1 becomes
-//         Z[i][d] = ((Z[i][d-1] | Z[i+1][d-1]) >> 1 | top) | Z[i+1][d-1]
+//         Z[i][d] = (Z[i][d-1] >> 1 | top) | (Z[i+1][d-1] >> 1 | top) | Z[i+1][d-1]
 //                 | ((Z[i+1][d] >> 1 | top) & EQ[text[i]])
-//     ten 32-bit operations per entry.  Before a lane's first row its inputs
-//     are zero and both shifted-in bits are off, so ramp steps leave it zero.
+//     where the shifted row d-1 of a column serves that column and its left
+//     neighbour: eight 32-bit operations per entry.  Before a lane's first
+//     row its inputs are zero and both shifted-in bits are off, so ramp steps
+//     leave it zero.
 //   * Early termination (Section 2.4.3): lane 0 of a group holds column 0;
 //     the first row whose entry has the msb of R clear is d_w, found by one
-//     ballot per step.  A wavefront's DC pass ends when no group is still
-//     computing.
+//     ballot per step; the group state is updated once per two steps.  A
+//     wavefront's DC pass ends when no group is still computing.
 //   * Stored entries (Section 2.4.1, entries not edges; Section 2.4.2, only
 //     columns 0..W-O are read by traceback) go to a per-group region of
 //     global memory, [row][column] with a row stride that is a multiple of
@@ -39,7 +41,9 @@
 //   * Traceback runs in lane 0 of every finished group, all groups of the
 //     wavefront together: match runs are skipped with an XOR of the 2-bit
 //     planes and a trailing-zero count, and each edit step reads row d-1 at
-//     columns i and i+1.
+//     columns i and i+1.  An event (match run, edit step) is one basic
+//     block, and the run list keeps the open run in place so that every
+//     update is one store.
 //   * Row budgets: a pass ends when every window it waits for has found
 //     d_w.  Plain mode waits for every window (rows 0..k_w at most).  Fixed
 //     mode waits for a window up to fixed_rows rows, learned mode up to the
@@ -120,7 +124,7 @@ __global__ __launch_bounds__(64) void cols_kernel(const AlignArgs a) {
     uint32_t nbslo = 0, nbshi = 0;     // row d-1 of column CB*q+CB
     uint32_t zrlo = 0, zrhi = 0;       // initial column at the lane's next row (used by q == L-1)
     int dl = 0;                        // row this lane computes at the next step
-    int gst = G_EMPTY;                 // group state, identical in the group's four lanes
+    int gst = G_EMPTY;                 // group state, identical in the group's L lanes
     int limit = 0, full = 0, dw = -1;
     uint32_t over_events = 0;
 
