@@ -472,7 +472,7 @@ __global__ __launch_bounds__(64) void cols_kernel(const AlignArgs a) {
                 }
             }
         }
-        // the group's four lanes learn that its traceback ended
+        // the group's L lanes learn that its traceback ended
         {
             const uint64_t tbm = __ballot(slot && gst == G_TB);
             if ((tbm & gbit) == 0 && gst == G_TB) gst = G_EMPTY;
