@@ -1,6 +1,5 @@
 // Device helpers of the column-block kernel: lane exchange, the initial
-// column, the run-length output and the in-place row update of Algorithm 1
-// on a lane's columns.
+// column and the in-place row update of Algorithm 1 on a lane's columns.
 #pragma once
 #include "internal.h"
 
@@ -17,20 +16,6 @@ __device__ __forceinline__ uint32_t from_upper_lane(uint32_t x) {
 __device__ __forceinline__ uint64_t z_init(int mw, int d) {
     const int s = mw - d;
     return s <= 0 ? ~0ull : (s >= 64 ? 0ull : (~0ull << s));
-}
-
-__device__ __forceinline__ int zbit(uint64_t z, int p) { return p >= 64 ? 1 : (int)((z >> p) & 1ull); }
-
-// Append `len` (>= 0) operations `op` to a pair's run list, merging equal
-// neighbours; len == 0 changes nothing.
-__device__ __forceinline__ void emit_run(int op, int len, int& cur_op, int& cur_len, int& nruns,
-                                         uint32_t* __restrict__ runs, int64_t roff, int64_t rcap) {
-    const bool same = cur_op == op;
-    const bool flush = !same && cur_len > 0 && len > 0;
-    if (flush && nruns < rcap) runs[roff + nruns] = ((uint32_t)cur_len << 2) | (uint32_t)cur_op;
-    nruns += flush ? 1 : 0;
-    cur_len = len == 0 ? cur_len : (same ? cur_len + len : len);
-    cur_op = len == 0 ? cur_op : op;
 }
 
 // One error row of the lane's CB columns: two VGPRs per column.
