@@ -42,6 +42,7 @@ struct scg_batch {
     Plane2* pplanes = nullptr;
     Plane2* tplanes = nullptr;
     int64_t pwords = 0, twords = 0;
+    int64_t pbytes = 0, tbytes = 0;   // input bytes (the packer reads no further)
     int64_t* pword_d = nullptr;
     int64_t* tword_d = nullptr;
     int32_t* plen_d = nullptr;
@@ -155,8 +156,10 @@ int enqueue_run(scg_batch* b, hipStream_t s, int32_t* edits, int32_t* text_end, 
         HIP_TRY(hipEventRecord(ev[0], s));
     }
     HIP_TRY(launch_reset(b->qctl_d, b->ring_d, b->qcap, b->order_d, b->stats_d, b->bad_d, b->npairs, s));
-    HIP_TRY(launch_pack(b->pat_d, b->pat_off_d, b->pword_d, b->npairs, b->pwords, b->pplanes, b->bad_d, c->num_cu, s));
-    HIP_TRY(launch_pack(b->txt_d, b->txt_off_d, b->tword_d, b->npairs, b->twords, b->tplanes, b->bad_d, c->num_cu, s));
+    HIP_TRY(launch_pack(b->pat_d, b->pat_off_d, b->pword_d, b->npairs, b->pwords, b->pbytes, b->pplanes, b->bad_d,
+                        c->num_cu, s));
+    HIP_TRY(launch_pack(b->txt_d, b->txt_off_d, b->tword_d, b->npairs, b->twords, b->tbytes, b->tplanes, b->bad_d,
+                        c->num_cu, s));
     if (with_events) HIP_TRY(hipEventRecord(ev[1], s));
     AlignArgs a{};
     a.pplanes = b->pplanes;
@@ -400,6 +403,8 @@ int scg_batch_create(scg_ctx* c, const scg_params* params, int32_t npairs, const
     }
     b->pwords = pw[npairs];
     b->twords = tw[npairs];
+    b->pbytes = pbytes;
+    b->tbytes = tbytes;
     // queue capacity: the initial order plus one entry per yield; a pair
     // yields only after advancing yield_chars pattern characters
     b->qcap = npairs;
@@ -695,9 +700,9 @@ int scg_features(scg_batch* b, int32_t nwin, const int32_t* windows, uint16_t* f
     hipStream_t s = (hipStream_t)stream;
     // planes are produced by the pack step of a run; make sure they exist
     HIP_TRY(launch_reset(b->qctl_d, b->ring_d, b->qcap, b->order_d, b->stats_d, b->bad_d, b->npairs, s));
-    HIP_TRY(launch_pack(b->pat_d, b->pat_off_d, b->pword_d, b->npairs, b->pwords, b->pplanes, b->bad_d,
+    HIP_TRY(launch_pack(b->pat_d, b->pat_off_d, b->pword_d, b->npairs, b->pwords, b->pbytes, b->pplanes, b->bad_d,
                         b->ctx->num_cu, s));
-    HIP_TRY(launch_pack(b->txt_d, b->txt_off_d, b->tword_d, b->npairs, b->twords, b->tplanes, b->bad_d,
+    HIP_TRY(launch_pack(b->txt_d, b->txt_off_d, b->tword_d, b->npairs, b->twords, b->tbytes, b->tplanes, b->bad_d,
                         b->ctx->num_cu, s));
     HIP_TRY(launch_features(b->pplanes, b->tplanes, b->pword_d, b->tword_d, b->plen_d, b->tlen_d, b->npairs, b->p.W,
                             nwin, windows, features, s));

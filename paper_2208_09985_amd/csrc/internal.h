@@ -82,7 +82,7 @@ struct AlignArgs {
 hipError_t launch_reset(uint32_t* qctl, int32_t* ring, int64_t qcap, const int32_t* order,
                         unsigned long long* stats, uint8_t* bad, int32_t npairs, hipStream_t s);
 hipError_t launch_pack(const uint8_t* seq, const int64_t* off, const int64_t* wordoff, int32_t npairs,
-                       int64_t total_words, Plane2* out, uint8_t* bad, int num_cu, hipStream_t s);
+                       int64_t total_words, int64_t total_bytes, Plane2* out, uint8_t* bad, int num_cu, hipStream_t s);
 hipError_t launch_align(const AlignArgs& a, int grid, size_t lds_bytes, hipStream_t s);
 size_t align_lds_bytes(int ccols, int ns);
 int align_max_blocks_per_cu(size_t lds_bytes, bool learned);

@@ -1,12 +1,12 @@
 // Encode + pack: ASCII sequences to the planar 2-bit layout (Plane2).
 //
 // The paper's implementations convert each pair to a two-bit-per-base
-// encoding before alignment (Section 2.5).  Here a wavefront produces eight
-// Plane2 (64 bases each) per iteration: for each, lane t loads byte t of the
-// slice (a coalesced 64-byte read; all eight loads are issued before the
-// first is used), and two ballots over the code bits are exactly the low and
-// high bit planes.  Lane 0 stores the 16-byte results.  The workload is a
-// single pass over the input bytes, so it is bound by HBM bandwidth.
+// encoding before alignment (Section 2.5).  Here a wavefront produces sixteen
+// Plane2 (64 bases each) per iteration from 1 KB of input staged in LDS with
+// 16-byte loads; for each word, lane t reads byte t of the word's 64 bases,
+// and two ballots over the code bits are exactly the low and high bit
+// planes.  Lane 0 stores the 16-byte results.  The workload is a single pass
+// over the input bytes, so it is bound by HBM bandwidth.
 #include "internal.h"
 
 namespace {
@@ -37,40 +37,59 @@ __device__ __forceinline__ int base_code(uint32_t c, bool& bad) {
 }
 
 // One workgroup per sequence (grid-stride over sequences): wave v of the
-// block packs words 8v..8v+7, 8v+32..8v+39, ... of its sequence, so no word
-// has to search for the sequence it belongs to.
+// block packs words 16v..16v+15, 16v+64..16v+79, ... of its sequence, so no
+// word has to search for the sequence it belongs to.  A wave stages the 1 KB
+// of its 16 words in LDS with one aligned 16-byte load per lane (the
+// chunk's start is arbitrary, so it loads from the 16-byte boundary below it
+// and one block more), then reads one byte per lane per word from LDS.
+constexpr int kChunkWords = 16;                 // words (64 bases each) per wave and iteration
+constexpr int kStageBlocks = kChunkWords * 4 + 1;   // 16-byte blocks staged: 1 KB and the misaligned tail
+
 __global__ __launch_bounds__(256) void pack_kernel(const uint8_t* __restrict__ seq, const int64_t* __restrict__ off,
-                                                   const int64_t* __restrict__ wordoff, int32_t npairs,
+                                                   const int64_t* __restrict__ wordoff, int32_t npairs, int64_t total,
                                                    Plane2* __restrict__ out, uint8_t* __restrict__ bad) {
+    __shared__ uint4 stage[4][kStageBlocks];
     const int lane = threadIdx.x & 63;
     const int wave = threadIdx.x >> 6;
+    const uint8_t* const sb = reinterpret_cast<const uint8_t*>(stage[wave]);
+    const uintptr_t sbase = reinterpret_cast<uintptr_t>(seq), send = sbase + (uintptr_t)total;
     for (int s = blockIdx.x; s < npairs; s += gridDim.x) {
         const int64_t start = off[s];
         const int64_t len = off[s + 1] - start;
         const int64_t w0 = wordoff[s];
         const int64_t nwords = wordoff[s + 1] - w0;   // (len + 63) / 64 + 1 padding word
         bool any_bad = false;
-        // kWords words per wavefront per iteration: their byte loads are all
-        // in flight before the first ballot needs one
-        constexpr int kWords = 8;
-        for (int64_t q0 = (int64_t)wave * kWords; q0 < nwords; q0 += 4 * kWords) {
-            uint32_t c[kWords];
-#pragma unroll
-            for (int u = 0; u < kWords; ++u) {
-                const int64_t pos = (q0 + u) * 64 + lane;
-                c[u] = pos < len ? seq[start + pos] : 'a';   // past the end: a valid placeholder, masked below
+        for (int64_t k0 = (int64_t)wave * kChunkWords; k0 < nwords; k0 += 4 * kChunkWords) {
+            // 16-byte blocks at absolute 16-byte boundaries: a block that holds a byte
+            // of the input lies in the input's pages, and blocks past its end are not read
+            const uintptr_t p0 = sbase + (uintptr_t)(start + k0 * 64);   // first byte of the chunk
+            const uintptr_t a0 = p0 & ~(uintptr_t)15;
+            const int sh = (int)(p0 - a0);
+            for (int blk = lane; blk < kStageBlocks; blk += 64) {
+                const uintptr_t ba = a0 + 16u * (uintptr_t)blk;
+                uint4 v{0u, 0u, 0u, 0u};
+                if (ba < send) v = *reinterpret_cast<const uint4*>(ba);
+                stage[wave][blk] = v;
             }
-#pragma unroll
-            for (int u = 0; u < kWords; ++u) {
-                const int64_t q = q0 + u;
+            // the wave reads bytes other lanes staged
+            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+            __builtin_amdgcn_wave_barrier();
+            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+#pragma unroll 4
+            for (int u = 0; u < kChunkWords; ++u) {
+                const int64_t q = k0 + u;
                 const int64_t pos = q * 64 + lane;
                 bool badc = false;
-                const int code = pos < len ? base_code(c[u], badc) : 0;
+                const int code = pos < len ? base_code(sb[sh + u * 64 + lane], badc) : 0;
                 const uint64_t plo = __ballot(code & 1);
                 const uint64_t phi = __ballot(code >> 1);
                 any_bad |= __ballot(badc) != 0;
                 if (lane == 0 && q < nwords) out[w0 + q] = Plane2{plo, phi};
             }
+            // the next iteration overwrites the staged bytes
+            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+            __builtin_amdgcn_wave_barrier();
+            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
         }
         if (lane == 0 && any_bad) bad[s] = 1;
     }
@@ -89,11 +108,12 @@ hipError_t launch_reset(uint32_t* qctl, int32_t* ring, int64_t qcap, const int32
 }
 
 hipError_t launch_pack(const uint8_t* seq, const int64_t* off, const int64_t* wordoff, int32_t npairs,
-                       int64_t total_words, Plane2* out, uint8_t* bad, int num_cu, hipStream_t s) {
+                       int64_t total_words, int64_t total_bytes, Plane2* out, uint8_t* bad, int num_cu, hipStream_t s) {
     if (total_words <= 0 || npairs <= 0) return hipSuccess;
     int64_t blocks = npairs;
     const int64_t cap = (int64_t)num_cu * 64;           // grid-stride over sequences beyond this
     if (blocks > cap) blocks = cap;
-    hipLaunchKernelGGL(pack_kernel, dim3((unsigned)blocks), dim3(256), 0, s, seq, off, wordoff, npairs, out, bad);
+    hipLaunchKernelGGL(pack_kernel, dim3((unsigned)blocks), dim3(256), 0, s, seq, off, wordoff, npairs, total_bytes, out,
+                       bad);
     return hipGetLastError();
 }
