@@ -1,8 +1,8 @@
 // Encode + pack: ASCII sequences to the planar 2-bit layout (Plane2).
 //
 // The paper's implementations convert each pair to a two-bit-per-base
-// encoding before alignment (Section 2.5).  Here a wavefront produces sixteen
-// Plane2 (64 bases each) per iteration from 1 KB of input staged in LDS with
+// encoding before alignment (Section 2.5).  Here a wavefront produces forty
+// Plane2 (64 bases each) per iteration from 2.5 KB of input staged in LDS with
 // 16-byte loads; for each word, lane t reads byte t of the word's 64 bases,
 // and two ballots over the code bits are exactly the low and high bit
 // planes.  Lane 0 stores the 16-byte results.  The workload is a single pass
@@ -37,13 +37,13 @@ __device__ __forceinline__ int base_code(uint32_t c, bool& bad) {
 }
 
 // One workgroup per sequence (grid-stride over sequences): wave v of the
-// block packs words 16v..16v+15, 16v+64..16v+79, ... of its sequence, so no
-// word has to search for the sequence it belongs to.  A wave stages the 1 KB
-// of its 16 words in LDS with one aligned 16-byte load per lane (the
+// block packs words 40v..40v+39, 40v+160..40v+199, ... of its sequence, so no
+// word has to search for the sequence it belongs to.  A wave stages the 2.5 KB
+// of its 40 words in LDS with aligned 16-byte loads (the
 // chunk's start is arbitrary, so it loads from the 16-byte boundary below it
 // and one block more), then reads one byte per lane per word from LDS.
-constexpr int kChunkWords = 16;                 // words (64 bases each) per wave and iteration
-constexpr int kStageBlocks = kChunkWords * 4 + 1;   // 16-byte blocks staged: 1 KB and the misaligned tail
+constexpr int kChunkWords = 40;                 // words (64 bases each) per wave and iteration (a 10 kbp read in one)
+constexpr int kStageBlocks = kChunkWords * 4 + 1;   // 16-byte blocks staged: the words and the misaligned tail
 
 __global__ __launch_bounds__(256) void pack_kernel(const uint8_t* __restrict__ seq, const int64_t* __restrict__ off,
                                                    const int64_t* __restrict__ wordoff, int32_t npairs, int64_t total,
