@@ -62,7 +62,6 @@ namespace {
 
 using namespace colblock;
 
-constexpr int kMaxGroups = 16;     // windows per wavefront, at most
 constexpr int kStoredRows = 64;    // rows 0..63 are kept for traceback
 
 // A group is RUN while the pass waits for it, OVER once it has used its row
