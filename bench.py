@@ -272,7 +272,7 @@ def main():
             e = summary(batch, sms, sst)
             ach = sst.ops_alg / (sst.kernel_ms_avg / 1e3) / 1e12
             e.update(windows=int(sst.windows), frac=round(ach / PEAK_T64OPS, 5),
-                     stored_entry_bits=32 if W - O <= 31 else (64 if W <= 64 else 128),
+                     stored_entry_bits=32 if W - O <= 31 else (48 if W - O <= 47 else (64 if W <= 64 else 128)),
                      mean_edits=round(float(np.mean(sres.edits[sres.status == 0])), 2),
                      aligned=int(np.sum(sres.status == 0)))
             sweep[f"W{W}_O{O}"] = e

@@ -37,7 +37,8 @@
 //     CB; each storing lane writes its CB columns with 16-byte stores.  When
 //     W-O <= 31 traceback reads bits 0..W-O only, so plain mode stores
 //     entries as their low 32 bits (NARROW; Section 2.4.2's narrower stored
-//     bitvectors).
+//     bitvectors); when W-O <= 47 it stores their low 48 bits as a 32-bit
+//     plane and a 16-bit plane (SPLIT), three quarters of the footprint.
 //   * Traceback runs in lane 0 of every finished group, all groups of the
 //     wavefront together: match runs are skipped with an XOR of the 2-bit
 //     planes and a trailing-zero count, and each edit step reads row d-1 at
@@ -82,8 +83,12 @@ struct GroupRec {      // LDS: what the slot lane tells its group at set-up
     int32_t pad;
 };
 
-template <bool LEARNED, int CB, bool NARROW>
+// ST: the stored entries.  0: whole 64-bit entries.  1 (NARROW): their low 32
+// bits, when traceback reads bits 0..31 at most.  2 (SPLIT): their low 48 bits
+// as a 32-bit plane and a 16-bit plane, when it reads bits 0..47 at most.
+template <bool LEARNED, int CB, int ST>
 __global__ __launch_bounds__(64) void cols_kernel(const AlignArgs a) {
+    constexpr bool NARROW = ST == 1, SPLIT = ST == 2;
     constexpr int NG = CB;          // windows per wavefront
     constexpr int L = 64 / NG;      // lanes per window
     __shared__ GroupRec grec[NG];
@@ -101,6 +106,10 @@ __global__ __launch_bounds__(64) void cols_kernel(const AlignArgs a) {
     const uint32_t gbyte = (uint32_t)(g * kStoredRows * stride) * 8u;
     const uint32_t qbyte = gbyte + (uint32_t)(CB * q) * ESZ;   // the lane's first column in row 0
     const uint32_t rowbytes = (uint32_t)stride * ESZ;
+    // SPLIT: rows of the 32-bit plane (stride*4 bytes) for rows 0..63, then rows
+    // of the 16-bit plane (stride*2 bytes)
+    const uint32_t lobytes = (uint32_t)stride * 4u, hibytes = (uint32_t)stride * 2u;
+    const uint32_t hiplane = gbyte + (uint32_t)kStoredRows * lobytes;
     const bool storer = CB * q < stride;
 
     if (lane < NG) grec[lane] = GroupRec{0, 0, 0, 0, 0, 0, 0, 0, CMD_NONE, 0};
@@ -312,6 +321,22 @@ __global__ __launch_bounds__(64) void cols_kernel(const AlignArgs a) {
                     if (NARROW) {
 #pragma unroll
                         for (int t = 0; t < CB; t += 4) row[t >> 2] = uint4{A.lo[t], A.lo[t + 1], A.lo[t + 2], A.lo[t + 3]};
+                    } else if (SPLIT) {
+                        // low words as they are; bits 32..47 two columns to a word
+                        uint4* lo = reinterpret_cast<uint4*>(bdent + (gbyte + __umul24((uint32_t)dh, lobytes) + (uint32_t)(CB * q) * 4u));
+#pragma unroll
+                        for (int t = 0; t < CB; t += 4) lo[t >> 2] = uint4{A.lo[t], A.lo[t + 1], A.lo[t + 2], A.lo[t + 3]};
+                        char* const hp = bdent + (hiplane + __umul24((uint32_t)dh, hibytes) + (uint32_t)(CB * q) * 2u);
+                        uint32_t hw[CB / 2];
+#pragma unroll
+                        for (int t = 0; t < CB; t += 2) hw[t >> 1] = __builtin_amdgcn_perm(A.hi[t + 1], A.hi[t], 0x05040100u);
+                        if constexpr (CB == 4) {
+                            *reinterpret_cast<uint2*>(hp) = uint2{hw[0], hw[1]};
+                        } else {
+#pragma unroll
+                            for (int t = 0; t < CB / 2; t += 4)
+                                reinterpret_cast<uint4*>(hp)[t >> 2] = uint4{hw[t], hw[t + 1], hw[t + 2], hw[t + 3]};
+                        }
                     } else {
 #pragma unroll
                         for (int t = 0; t < CB; t += 2) row[t >> 1] = uint4{A.lo[t], A.hi[t], A.lo[t + 1], A.hi[t + 1]};
@@ -401,6 +426,17 @@ __global__ __launch_bounds__(64) void cols_kernel(const AlignArgs a) {
                     if (NARROW) {
                         v0 = *reinterpret_cast<const uint32_t*>(e0);
                         v1 = *reinterpret_cast<const uint32_t*>(e1);
+                    } else if (SPLIT) {
+                        // columns ti and ti+1 of both planes, as one 8-byte word each (the
+                        // 16-bit word from the 4-byte boundary at or below column ti)
+                        struct __attribute__((packed, aligned(4))) W2 { uint64_t v; };
+                        const uint32_t rr = (uint32_t)(max(td, 1) - 1);
+                        const uint32_t c0 = (uint32_t)min(ti, stride - 1);
+                        const uint64_t lw = reinterpret_cast<const W2*>(bdent + (gbyte + __umul24(rr, lobytes) + c0 * 4u))->v;
+                        const uint64_t hw = reinterpret_cast<const W2*>(bdent + (hiplane + __umul24(rr, hibytes) + (c0 & ~1u) * 2u))->v
+                                            >> ((c0 & 1u) * 16u);
+                        v0 = (uint64_t)(uint32_t)lw | (uint64_t)(hw & 0xFFFFu) << 32;
+                        v1 = (lw >> 32) | (uint64_t)((hw >> 16) & 0xFFFFu) << 32;
                     } else {
                         v0 = *reinterpret_cast<const uint64_t*>(e0);
                         v1 = *reinterpret_cast<const uint64_t*>(e1);
@@ -507,53 +543,59 @@ size_t cols_dent_bytes(int grid, int cap, int ng) {
     return (size_t)grid * ng * kStoredRows * (size_t)cols_dent_stride(cap, ng) * sizeof(uint64_t);
 }
 
-// 32-bit stored entries when traceback reads bits 0..31 at most; the learned
-// form keeps 64-bit entries at every W-O
-static bool cols_narrow(bool learned, int cap) { return !learned && cap <= 31; }
+// 32-bit stored entries when traceback reads bits 0..31 at most, 48-bit ones
+// (two planes) when it reads bits 0..47 at most; the learned form keeps 64-bit
+// entries at every W-O
+static int cols_store(bool learned, int cap) { return learned ? 0 : (cap <= 31 ? 1 : (cap <= 47 ? 2 : 0)); }
 
-template <bool LEARNED, bool NARROW>
+template <bool LEARNED, int ST>
 static const void* cols_fn(int ng) {
     switch (ng) {
-    case 4: return (const void*)cols_kernel<LEARNED, 4, NARROW>;
-    case 8: return (const void*)cols_kernel<LEARNED, 8, NARROW>;
-    default: return (const void*)cols_kernel<LEARNED, 16, NARROW>;
+    case 4: return (const void*)cols_kernel<LEARNED, 4, ST>;
+    case 8: return (const void*)cols_kernel<LEARNED, 8, ST>;
+    default: return (const void*)cols_kernel<LEARNED, 16, ST>;
     }
 }
 
 // plain mode also has 32 windows per wavefront: two lanes per window, 32
 // columns each (the lane-per-pair end of the mapping)
-template <bool NARROW>
+template <int ST>
 static const void* cols_fn_plain(int ng) {
-    return ng == 32 ? (const void*)cols_kernel<false, 32, NARROW> : cols_fn<false, NARROW>(ng);
+    return ng == 32 ? (const void*)cols_kernel<false, 32, ST> : cols_fn<false, ST>(ng);
 }
 
 int cols_max_blocks_per_cu(bool learned, int ng, size_t lds, int cap) {
     int nb = 0;
-    const void* f = learned ? cols_fn<true, false>(ng)
-                            : (cols_narrow(false, cap) ? cols_fn_plain<true>(ng) : cols_fn_plain<false>(ng));
+    const int st = cols_store(learned, cap);
+    const void* f = learned ? cols_fn<true, 0>(ng)
+                  : (st == 1 ? cols_fn_plain<1>(ng) : (st == 2 ? cols_fn_plain<2>(ng) : cols_fn_plain<0>(ng)));
     if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, f, 64, lds) != hipSuccess) return 1;
     return nb < 1 ? 1 : nb;
 }
 
 hipError_t launch_align_cols(const AlignArgs& a, int grid, int ng, size_t lds, hipStream_t s) {
     const bool learned = a.mode == 1;
-    const bool narrow = cols_narrow(learned, a.cap);
-#define SCG_COLS_LAUNCH(LRN, NGV, NRW) hipLaunchKernelGGL((cols_kernel<LRN, NGV, NRW>), dim3(grid), dim3(64), lds, s, a)
+    const int st = cols_store(learned, a.cap);
+#define SCG_COLS_LAUNCH(LRN, NGV, STV) hipLaunchKernelGGL((cols_kernel<LRN, NGV, STV>), dim3(grid), dim3(64), lds, s, a)
+#define SCG_COLS_PLAIN(STV)                          \
+    do {                                             \
+        if (ng == 4) SCG_COLS_LAUNCH(false, 4, STV);        \
+        else if (ng == 8) SCG_COLS_LAUNCH(false, 8, STV);   \
+        else if (ng == 16) SCG_COLS_LAUNCH(false, 16, STV); \
+        else SCG_COLS_LAUNCH(false, 32, STV);               \
+    } while (0)
     if (learned) {
-        if (ng == 4) SCG_COLS_LAUNCH(true, 4, false);
-        else if (ng == 8) SCG_COLS_LAUNCH(true, 8, false);
-        else SCG_COLS_LAUNCH(true, 16, false);
-    } else if (narrow) {
-        if (ng == 4) SCG_COLS_LAUNCH(false, 4, true);
-        else if (ng == 8) SCG_COLS_LAUNCH(false, 8, true);
-        else if (ng == 16) SCG_COLS_LAUNCH(false, 16, true);
-        else SCG_COLS_LAUNCH(false, 32, true);
+        if (ng == 4) SCG_COLS_LAUNCH(true, 4, 0);
+        else if (ng == 8) SCG_COLS_LAUNCH(true, 8, 0);
+        else SCG_COLS_LAUNCH(true, 16, 0);
+    } else if (st == 1) {
+        SCG_COLS_PLAIN(1);
+    } else if (st == 2) {
+        SCG_COLS_PLAIN(2);
     } else {
-        if (ng == 4) SCG_COLS_LAUNCH(false, 4, false);
-        else if (ng == 8) SCG_COLS_LAUNCH(false, 8, false);
-        else if (ng == 16) SCG_COLS_LAUNCH(false, 16, false);
-        else SCG_COLS_LAUNCH(false, 32, false);
+        SCG_COLS_PLAIN(0);
     }
+#undef SCG_COLS_PLAIN
 #undef SCG_COLS_LAUNCH
     return hipGetLastError();
 }

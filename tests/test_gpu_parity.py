@@ -75,7 +75,7 @@ def test_uneven_and_mixed_samples(ctx):
 
 
 @pytest.mark.parametrize("W,O,k", [(64, 33, 64), (32, 17, 32), (16, 9, 16), (8, 3, 8), (4, 3, 4), (64, 0, 64),
-                                   (64, 63, 64), (1, 0, 1), (48, 20, 30), (64, 24, 6)])
+                                   (64, 63, 64), (1, 0, 1), (48, 20, 30), (64, 24, 6), (64, 17, 64), (64, 16, 64)])
 def test_window_parameters(ctx, W, O, k):
     rng = np.random.default_rng(W * 100 + O)
     pats, txts = [], []
