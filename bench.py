@@ -107,6 +107,12 @@ def spec(t):
     return t[1] if t[0] == "fixed" else f"{t[0]}{tuple(t[1:])}"
 
 
+def stored_form(cap):
+    """Template argument of the plain column-block kernel for W - O = cap: 1 keeps
+    32-bit entries, 2 keeps 48-bit entries in two planes, 0 whole 64-bit ones."""
+    return 1 if cap <= 31 else (2 if cap <= 47 else 0)
+
+
 def kernel_source_hash() -> str:
     """Hash of the measured kernel's sources with comments and blank space
     removed, so that the counters stay valid across comment-only edits (the
@@ -272,7 +278,7 @@ def main():
             e = summary(batch, sms, sst)
             ach = sst.ops_alg / (sst.kernel_ms_avg / 1e3) / 1e12
             e.update(windows=int(sst.windows), frac=round(ach / PEAK_T64OPS, 5),
-                     stored_entry_bits=32 if W - O <= 31 else (48 if W - O <= 47 else (64 if W <= 64 else 128)),
+                     stored_entry_bits=(128 if W > 64 else {1: 32, 2: 48, 0: 64}[stored_form(W - O)]),
                      mean_edits=round(float(np.mean(sres.edits[sres.status == 0])), 2),
                      aligned=int(np.sum(sres.status == 0)))
             sweep[f"W{W}_O{O}"] = e
@@ -329,7 +335,7 @@ def main():
         "roofline": {"bound": "alu", "achieved": round(achieved, 4), "peak": round(PEAK_T64OPS, 3),
                      "unit": "T 64-bit op/s", "frac": round(achieved / PEAK_T64OPS, 5),
                      "traffic": measured_traffic("cols_kernel_plain"),
-                     "kernel": "cols_kernel<false, 8>", "kernel_ms": round(st.kernel_ms_avg, 4),
+                     "kernel": f"cols_kernel<false, 8, {stored_form(w.W - w.O)}>", "kernel_ms": round(st.kernel_ms_avg, 4),
                      "ops_alg_per_launch": int(st.ops_alg), "windows_per_launch": int(st.windows)},
         "variants": variants,
         "workloads": workloads,
