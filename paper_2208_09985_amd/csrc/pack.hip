@@ -5,8 +5,13 @@
 // Plane2 (64 bases each) per iteration from 2.5 KB of input staged in LDS with
 // 16-byte loads; for each word, lane t reads byte t of the word's 64 bases,
 // and two ballots over the code bits are exactly the low and high bit
-// planes.  Lane 0 stores the 16-byte results.  The workload is a single pass
-// over the input bytes, so it is bound by HBM bandwidth.
+// planes.  Lane u collects word u's planes, and one store writes all forty.
+// The workload is a single pass over the input bytes, so it is bound by HBM
+// bandwidth.
+//
+// The code of a base is bits 1 and 2 of its ASCII byte: A 0, C 1, T 2, G 3,
+// the same for lower case (bit 5 is the case bit).  The kernels only compare
+// codes for equality, so any one-to-one code of the four bases serves.
 #include "internal.h"
 
 namespace {
@@ -26,14 +31,10 @@ __global__ __launch_bounds__(256) void reset_kernel(uint32_t* qctl, int32_t* rin
     for (int64_t x = t; x < qcap; x += stride) ring[x] = x < npairs ? order[x] + 1 : 0;
 }
 
-__device__ __forceinline__ int base_code(uint32_t c, bool& bad) {
-    switch (c | 0x20u) {  // fold to lower case
-    case 'a': return 0;
-    case 'c': return 1;
-    case 'g': return 2;
-    case 't': return 3;
-    default: bad = true; return 0;
-    }
+// 1 for the bytes a, c, g, t in either case, else 0
+__device__ __forceinline__ uint32_t is_base(uint32_t c) {
+    const uint32_t x = (c | 0x20u) - (uint32_t)'a';   // a 0, c 2, g 6, t 19
+    return x < 20u ? (0x80045u >> x) & 1u : 0u;
 }
 
 // One workgroup per sequence (grid-stride over sequences): wave v of the
@@ -58,7 +59,7 @@ __global__ __launch_bounds__(256) void pack_kernel(const uint8_t* __restrict__ s
         const int64_t len = off[s + 1] - start;
         const int64_t w0 = wordoff[s];
         const int64_t nwords = wordoff[s + 1] - w0;   // (len + 63) / 64 + 1 padding word
-        bool any_bad = false;
+        uint32_t bad_lane = 0;   // a non-base byte seen by this lane
         for (int64_t k0 = (int64_t)wave * kChunkWords; k0 < nwords; k0 += 4 * kChunkWords) {
             // 16-byte blocks at absolute 16-byte boundaries: a block that holds a byte
             // of the input lies in the input's pages, and blocks past its end are not read
@@ -75,23 +76,31 @@ __global__ __launch_bounds__(256) void pack_kernel(const uint8_t* __restrict__ s
             __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
             __builtin_amdgcn_wave_barrier();
             __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-#pragma unroll 4
+            // word u's planes go to lane u (lo.x, lo.y, hi.x, hi.y)
+            uint32_t w_lo0 = 0, w_lo1 = 0, w_hi0 = 0, w_hi1 = 0;
+            // bases of the sequence in this chunk
+            const int rem = (int)max((int64_t)0, min(len - k0 * 64, (int64_t)(kChunkWords * 64)));
+#pragma unroll 8
             for (int u = 0; u < kChunkWords; ++u) {
-                const int64_t q = k0 + u;
-                const int64_t pos = q * 64 + lane;
-                bool badc = false;
-                const int code = pos < len ? base_code(sb[sh + u * 64 + lane], badc) : 0;
-                const uint64_t plo = __ballot(code & 1);
-                const uint64_t phi = __ballot(code >> 1);
-                any_bad |= __ballot(badc) != 0;
-                if (lane == 0 && q < nwords) out[w0 + q] = Plane2{plo, phi};
+                const uint32_t c = sb[sh + u * 64 + lane];
+                const bool in = u * 64 + lane < rem;
+                bad_lane |= in ? (is_base(c) ^ 1u) : 0u;
+                const uint64_t plo = __ballot(in && (c & 2u) != 0);
+                const uint64_t phi = __ballot(in && (c & 4u) != 0);
+                const bool mine = lane == u;
+                w_lo0 = mine ? (uint32_t)plo : w_lo0;
+                w_lo1 = mine ? (uint32_t)(plo >> 32) : w_lo1;
+                w_hi0 = mine ? (uint32_t)phi : w_hi0;
+                w_hi1 = mine ? (uint32_t)(phi >> 32) : w_hi1;
             }
+            if (lane < kChunkWords && k0 + lane < nwords)
+                out[w0 + k0 + lane] = Plane2{(uint64_t)w_lo1 << 32 | w_lo0, (uint64_t)w_hi1 << 32 | w_hi0};
             // the next iteration overwrites the staged bytes
             __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
             __builtin_amdgcn_wave_barrier();
             __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
         }
-        if (lane == 0 && any_bad) bad[s] = 1;
+        if (__ballot(bad_lane != 0) != 0 && lane == 0) bad[s] = 1;
     }
 }
 
