@@ -79,13 +79,20 @@ struct GroupRecW {     // LDS: what the slot lane tells its group at set-up
     int32_t m_w, n_w, full, fresh;
 };
 
+// a stored entry's low 96 bits
+struct __attribute__((packed, aligned(4))) W3 {
+    uint32_t x, y, z;
+};
+
 __device__ __forceinline__ uint32_t word_of(V128 v, int k) {
     return (uint32_t)((k < 2 ? v.lo : v.hi) >> (32 * (k & 1)));
 }
 
 // Occupancy target: three wavefronts per SIMD with 4 windows each (168
 // VGPRs), two with 8 (256), so that 10,000 pairs are resident at once.
-template <int NG>
+// N96: traceback reads bits 0..W-O <= 95 only, so the stored entries keep their
+// low 96 bits (12 bytes) and word 3 is never written or read.
+template <int NG, bool N96>
 __global__ __launch_bounds__(64, NG == 4 ? 3 : 2) void wide_kernel(const AlignArgs a) {
     constexpr int L = 64 / NG;      // lanes per window
     constexpr int CB = 128 / L;     // columns per lane
@@ -95,13 +102,14 @@ __global__ __launch_bounds__(64, NG == 4 ? 3 : 2) void wide_kernel(const AlignAr
     const bool slot = q == 0;
     const uint64_t gbit = 1ull << (lane - q);   // the group's slot lane in a ballot
     const int cap = a.cap;
-    const int stride = a.dstride;               // stored entries per row (16 bytes each)
+    const int stride = a.dstride;               // stored entries per row (16 or 12 bytes each)
     // the block's stored rows start at a wavefront-uniform address; a lane reaches its
     // group's entries with a 32-bit byte offset (a group holds 128 rows of `stride` entries)
     char* const bdent = reinterpret_cast<char*>(reinterpret_cast<uint4*>(a.dent) + (size_t)blockIdx.x * NG * (size_t)(kRowsW * stride));
     const uint32_t gbyte = (uint32_t)(g * kRowsW * stride) * 16u;
-    const uint32_t qbyte = gbyte + (uint32_t)(CB * q) * 16u;   // the lane's first column in row 0
-    const uint32_t rowbytes = (uint32_t)stride * 16u;
+    constexpr uint32_t ESZ = N96 ? 12u : 16u;                  // bytes per stored entry
+    const uint32_t qbyte = gbyte + (uint32_t)(CB * q) * ESZ;   // the lane's first column in row 0
+    const uint32_t rowbytes = (uint32_t)stride * ESZ;
     const bool storer = CB * q < stride;
 
     if (lane < NG) grec[lane] = GroupRecW{{0, 0}, {0, 0}, {0, 0}, {0, 0}, 0, 0, 0, 0};
@@ -326,8 +334,14 @@ __global__ __launch_bounds__(64, NG == 4 ? 3 : 2) void wide_kernel(const AlignAr
             // keep the row for traceback
             if (computing && storer && dl >= 0 && dl < kRowsW) {
                 uint4* row = reinterpret_cast<uint4*>(bdent + (qbyte + __umul24((uint32_t)dl, rowbytes)));
+                if constexpr (N96) {
+                    W3* const row3 = reinterpret_cast<W3*>(row);
 #pragma unroll
-                for (int t = 0; t < CB; ++t) row[t] = uint4{A[0][t], A[1][t], A[2][t], A[3][t]};
+                    for (int t = 0; t < CB; ++t) row3[t] = W3{A[0][t], A[1][t], A[2][t]};
+                } else {
+#pragma unroll
+                    for (int t = 0; t < CB; ++t) row[t] = uint4{A[0][t], A[1][t], A[2][t], A[3][t]};
+                }
             }
             // early termination: column 0 of row d has the msb of R clear
             const uint64_t hb = __ballot(slot && computing && dl >= 0 && (A[0][0] & 1u));
@@ -394,8 +408,17 @@ __global__ __launch_bounds__(64, NG == 4 ? 3 : 2) void wide_kernel(const AlignAr
                     // edit step at (ti, tj, td): bits tj, tj+1 of row td-1 at columns ti and ti+1.
                     // The loads go out first; the run bookkeeping below overlaps them.
                     const uint32_t ro = gbyte + __umul24((uint32_t)(max(td, 1) - 1), rowbytes);
-                    const uint4 e0 = *reinterpret_cast<const uint4*>(bdent + (ro + (uint32_t)min(ti, stride - 1) * 16u));
-                    const uint4 e1 = *reinterpret_cast<const uint4*>(bdent + (ro + (uint32_t)min(ti + 1, stride - 1) * 16u));
+                    const char* const p0e = bdent + (ro + (uint32_t)min(ti, stride - 1) * ESZ);
+                    const char* const p1e = bdent + (ro + (uint32_t)min(ti + 1, stride - 1) * ESZ);
+                    uint4 e0, e1;
+                    if constexpr (N96) {
+                        const W3 a0 = *reinterpret_cast<const W3*>(p0e), a1 = *reinterpret_cast<const W3*>(p1e);
+                        e0 = uint4{a0.x, a0.y, a0.z, 0u};
+                        e1 = uint4{a1.x, a1.y, a1.z, 0u};
+                    } else {
+                        e0 = *reinterpret_cast<const uint4*>(p0e);
+                        e1 = *reinterpret_cast<const uint4*>(p1e);
+                    }
                     // the run list always holds the open run at index nruns, so
                     // extending or starting a run is one unconditional store
                     {
@@ -482,15 +505,24 @@ size_t wide_dent_bytes(int grid, int cap, int ng) {
     return (size_t)grid * ng * kRowsW * (size_t)wide_dent_stride(cap, ng) * 16u;
 }
 
-int wide_max_blocks_per_cu(int ng) {
+static const void* wide_fn(int ng, bool n96) {
+    if (n96) return ng == 8 ? (const void*)wide_kernel<8, true> : (const void*)wide_kernel<4, true>;
+    return ng == 8 ? (const void*)wide_kernel<8, false> : (const void*)wide_kernel<4, false>;
+}
+
+int wide_max_blocks_per_cu(int ng, int cap) {
     int nb = 0;
-    const void* f = ng == 8 ? (const void*)wide_kernel<8> : (const void*)wide_kernel<4>;
+    const void* f = wide_fn(ng, cap <= 95);
     if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, f, 64, 0) != hipSuccess) return 1;
     return nb < 1 ? 1 : nb;
 }
 
 hipError_t launch_align_wide(const AlignArgs& a, int grid, int ng, hipStream_t s) {
-    if (ng == 8) hipLaunchKernelGGL((wide_kernel<8>), dim3(grid), dim3(64), 0, s, a);
-    else hipLaunchKernelGGL((wide_kernel<4>), dim3(grid), dim3(64), 0, s, a);
+    // 12-byte stored entries when traceback reads bits 0..95 at most
+    const bool n96 = a.cap <= 95;
+    if (ng == 8 && n96) hipLaunchKernelGGL((wide_kernel<8, true>), dim3(grid), dim3(64), 0, s, a);
+    else if (ng == 8) hipLaunchKernelGGL((wide_kernel<8, false>), dim3(grid), dim3(64), 0, s, a);
+    else if (n96) hipLaunchKernelGGL((wide_kernel<4, true>), dim3(grid), dim3(64), 0, s, a);
+    else hipLaunchKernelGGL((wide_kernel<4, false>), dim3(grid), dim3(64), 0, s, a);
     return hipGetLastError();
 }

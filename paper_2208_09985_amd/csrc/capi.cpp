@@ -463,7 +463,7 @@ int scg_batch_create(scg_ctx* c, const scg_params* params, int32_t npairs, const
         if (params->slots > 0) b->ns = params->slots > 4 ? 8 : 4;
         else b->ns = npairs >= 8 * c->num_cu ? 8 : 4;
         b->lds = 0;
-        per_cu = wide_max_blocks_per_cu(b->ns);
+        per_cu = wide_max_blocks_per_cu(b->ns, params->W - params->O);
     } else if (b->cols) {
         // windows per wavefront: 4, 8 or 16; automatic = enough wavefronts to
         // give every SIMD two of them

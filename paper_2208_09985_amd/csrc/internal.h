@@ -93,7 +93,7 @@ int cols_max_blocks_per_cu(bool learned, int ng, size_t lds, int cap);
 hipError_t launch_align_wide(const AlignArgs& a, int grid, int ng, hipStream_t s);
 int wide_dent_stride(int cap, int ng);
 size_t wide_dent_bytes(int grid, int cap, int ng);
-int wide_max_blocks_per_cu(int ng);
+int wide_max_blocks_per_cu(int ng, int cap);
 hipError_t launch_features(const Plane2* pplanes, const Plane2* tplanes, const int64_t* pword,
                            const int64_t* tword, const int32_t* plen, const int32_t* tlen, int32_t npairs,
                            int32_t W, int32_t nwin, const int32_t* windows, uint16_t* features, hipStream_t s);

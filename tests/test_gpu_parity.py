@@ -260,7 +260,8 @@ def test_one_shot_batch_call(ctx):
 
 
 @pytest.mark.parametrize("W,O,k,slots", [(128, 24, 128, 0), (128, 64, 128, 8), (96, 32, 96, 0), (65, 0, 65, 4),
-                                         (128, 127, 128, 0), (100, 40, 30, 8), (128, 24, 5, 0)])
+                                         (128, 127, 128, 0), (100, 40, 30, 8), (128, 24, 5, 0), (128, 33, 128, 8),
+                                         (128, 32, 128, 8)])
 def test_wide_windows(ctx, W, O, k, slots):
     # windows of 65..128 characters (wide kernel), against the oracle's 128-bit instantiation
     rng = np.random.default_rng(W * 1000 + O * 10 + k)
