@@ -278,7 +278,7 @@ def main():
             e = summary(batch, sms, sst)
             ach = sst.ops_alg / (sst.kernel_ms_avg / 1e3) / 1e12
             e.update(windows=int(sst.windows), frac=round(ach / PEAK_T64OPS, 5),
-                     stored_entry_bits=(128 if W > 64 else {1: 32, 2: 48, 0: 64}[stored_form(W - O)]),
+                     stored_entry_bits=((96 if W - O <= 95 else 128) if W > 64 else {1: 32, 2: 48, 0: 64}[stored_form(W - O)]),
                      mean_edits=round(float(np.mean(sres.edits[sres.status == 0])), 2),
                      aligned=int(np.sum(sres.status == 0)))
             sweep[f"W{W}_O{O}"] = e
