@@ -18,8 +18,10 @@
 //     column 0, and one ballot per step finds the first row whose entry has
 //     the msb of R clear.
 //   * Entries of rows 0..127, columns 0..min(W-O, 127) (Sections 2.4.1 and
-//     2.4.2) go to a per-group region of global memory, 16 bytes per entry;
-//     the traceback of each finished window runs in its group's lane 0.
+//     2.4.2) go to a per-group region of global memory, 16 bytes per entry,
+//     or 12 (the low 96 bits) when W-O <= 95, as traceback reads bits
+//     0..W-O only; the traceback of each finished window runs in its
+//     group's lane 0.
 #include "colblock.h"
 
 namespace {
