@@ -19,9 +19,9 @@
 //     the msb of R clear.
 //   * Entries of rows 0..127, columns 0..min(W-O, 127) (Sections 2.4.1 and
 //     2.4.2) go to a per-group region of global memory, 16 bytes per entry,
-//     or 12 (the low 96 bits) when W-O <= 95, as traceback reads bits
-//     0..W-O only; the traceback of each finished window runs in its
-//     group's lane 0.
+//     or 12 (the low 96 bits) when W-O <= 95 and 8 when W-O <= 63, as
+//     traceback reads bits 0..W-O only; the traceback of each finished
+//     window runs in its group's lane 0.
 #include "colblock.h"
 
 namespace {
@@ -92,9 +92,10 @@ __device__ __forceinline__ uint32_t word_of(V128 v, int k) {
 
 // Occupancy target: three wavefronts per SIMD with 4 windows each (168
 // VGPRs), two with 8 (256), so that 10,000 pairs are resident at once.
-// N96: traceback reads bits 0..W-O <= 95 only, so the stored entries keep their
-// low 96 bits (12 bytes) and word 3 is never written or read.
-template <int NG, bool N96>
+// SW: 32-bit words kept per stored entry.  Traceback reads bits 0..W-O only, so
+// with W-O <= 95 the entries keep their low 96 bits (SW = 3) and with W-O <= 63
+// their low 64 (SW = 2); the other words are never written or read.
+template <int NG, int SW>
 __global__ __launch_bounds__(64, NG == 4 ? 3 : 2) void wide_kernel(const AlignArgs a) {
     constexpr int L = 64 / NG;      // lanes per window
     constexpr int CB = 128 / L;     // columns per lane
@@ -109,7 +110,7 @@ __global__ __launch_bounds__(64, NG == 4 ? 3 : 2) void wide_kernel(const AlignAr
     // group's entries with a 32-bit byte offset (a group holds 128 rows of `stride` entries)
     char* const bdent = reinterpret_cast<char*>(reinterpret_cast<uint4*>(a.dent) + (size_t)blockIdx.x * NG * (size_t)(kRowsW * stride));
     const uint32_t gbyte = (uint32_t)(g * kRowsW * stride) * 16u;
-    constexpr uint32_t ESZ = N96 ? 12u : 16u;                  // bytes per stored entry
+    constexpr uint32_t ESZ = 4u * SW;                          // bytes per stored entry
     const uint32_t qbyte = gbyte + (uint32_t)(CB * q) * ESZ;   // the lane's first column in row 0
     const uint32_t rowbytes = (uint32_t)stride * ESZ;
     const bool storer = CB * q < stride;
@@ -336,7 +337,11 @@ __global__ __launch_bounds__(64, NG == 4 ? 3 : 2) void wide_kernel(const AlignAr
             // keep the row for traceback
             if (computing && storer && dl >= 0 && dl < kRowsW) {
                 uint4* row = reinterpret_cast<uint4*>(bdent + (qbyte + __umul24((uint32_t)dl, rowbytes)));
-                if constexpr (N96) {
+                if constexpr (SW == 2) {
+                    uint2* const row2 = reinterpret_cast<uint2*>(row);
+#pragma unroll
+                    for (int t = 0; t < CB; ++t) row2[t] = uint2{A[0][t], A[1][t]};
+                } else if constexpr (SW == 3) {
                     W3* const row3 = reinterpret_cast<W3*>(row);
 #pragma unroll
                     for (int t = 0; t < CB; ++t) row3[t] = W3{A[0][t], A[1][t], A[2][t]};
@@ -413,7 +418,11 @@ __global__ __launch_bounds__(64, NG == 4 ? 3 : 2) void wide_kernel(const AlignAr
                     const char* const p0e = bdent + (ro + (uint32_t)min(ti, stride - 1) * ESZ);
                     const char* const p1e = bdent + (ro + (uint32_t)min(ti + 1, stride - 1) * ESZ);
                     uint4 e0, e1;
-                    if constexpr (N96) {
+                    if constexpr (SW == 2) {
+                        const uint2 a0 = *reinterpret_cast<const uint2*>(p0e), a1 = *reinterpret_cast<const uint2*>(p1e);
+                        e0 = uint4{a0.x, a0.y, 0u, 0u};
+                        e1 = uint4{a1.x, a1.y, 0u, 0u};
+                    } else if constexpr (SW == 3) {
                         const W3 a0 = *reinterpret_cast<const W3*>(p0e), a1 = *reinterpret_cast<const W3*>(p1e);
                         e0 = uint4{a0.x, a0.y, a0.z, 0u};
                         e1 = uint4{a1.x, a1.y, a1.z, 0u};
@@ -507,24 +516,34 @@ size_t wide_dent_bytes(int grid, int cap, int ng) {
     return (size_t)grid * ng * kRowsW * (size_t)wide_dent_stride(cap, ng) * 16u;
 }
 
-static const void* wide_fn(int ng, bool n96) {
-    if (n96) return ng == 8 ? (const void*)wide_kernel<8, true> : (const void*)wide_kernel<4, true>;
-    return ng == 8 ? (const void*)wide_kernel<8, false> : (const void*)wide_kernel<4, false>;
+// words kept per stored entry for W - O = cap
+static int wide_words(int cap) { return cap <= 63 ? 2 : (cap <= 95 ? 3 : 4); }
+
+static const void* wide_fn(int ng, int sw) {
+    if (sw == 2) return ng == 8 ? (const void*)wide_kernel<8, 2> : (const void*)wide_kernel<4, 2>;
+    if (sw == 3) return ng == 8 ? (const void*)wide_kernel<8, 3> : (const void*)wide_kernel<4, 3>;
+    return ng == 8 ? (const void*)wide_kernel<8, 4> : (const void*)wide_kernel<4, 4>;
 }
 
 int wide_max_blocks_per_cu(int ng, int cap) {
     int nb = 0;
-    const void* f = wide_fn(ng, cap <= 95);
+    const void* f = wide_fn(ng, wide_words(cap));
     if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, f, 64, 0) != hipSuccess) return 1;
     return nb < 1 ? 1 : nb;
 }
 
 hipError_t launch_align_wide(const AlignArgs& a, int grid, int ng, hipStream_t s) {
-    // 12-byte stored entries when traceback reads bits 0..95 at most
-    const bool n96 = a.cap <= 95;
-    if (ng == 8 && n96) hipLaunchKernelGGL((wide_kernel<8, true>), dim3(grid), dim3(64), 0, s, a);
-    else if (ng == 8) hipLaunchKernelGGL((wide_kernel<8, false>), dim3(grid), dim3(64), 0, s, a);
-    else if (n96) hipLaunchKernelGGL((wide_kernel<4, true>), dim3(grid), dim3(64), 0, s, a);
-    else hipLaunchKernelGGL((wide_kernel<4, false>), dim3(grid), dim3(64), 0, s, a);
+    const int sw = wide_words(a.cap);
+#define SCG_WIDE_LAUNCH(NGV, SWV) hipLaunchKernelGGL((wide_kernel<NGV, SWV>), dim3(grid), dim3(64), 0, s, a)
+    if (ng == 8) {
+        if (sw == 2) SCG_WIDE_LAUNCH(8, 2);
+        else if (sw == 3) SCG_WIDE_LAUNCH(8, 3);
+        else SCG_WIDE_LAUNCH(8, 4);
+    } else {
+        if (sw == 2) SCG_WIDE_LAUNCH(4, 2);
+        else if (sw == 3) SCG_WIDE_LAUNCH(4, 3);
+        else SCG_WIDE_LAUNCH(4, 4);
+    }
+#undef SCG_WIDE_LAUNCH
     return hipGetLastError();
 }
