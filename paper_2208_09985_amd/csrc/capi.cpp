@@ -459,9 +459,11 @@ int scg_batch_create(scg_ctx* c, const scg_params* params, int32_t npairs, const
     int per_cu;
     if (b->wide) {
         // 4 or 8 windows per wavefront (16 or 8 lanes of 8 or 16 columns each);
-        // automatic: 8 once that still gives every SIMD a wavefront
+        // automatic: 8 with whole 128-bit entries (W - O > 95) once that still
+        // gives every SIMD a wavefront, else 4 (with 8- or 12-byte entries the
+        // larger grid of four-window wavefronts is the faster one)
         if (params->slots > 0) b->ns = params->slots > 4 ? 8 : 4;
-        else b->ns = npairs >= 8 * c->num_cu ? 8 : 4;
+        else b->ns = (params->W - params->O > 95 && npairs >= 8 * c->num_cu) ? 8 : 4;
         b->lds = 0;
         per_cu = wide_max_blocks_per_cu(b->ns, params->W - params->O);
     } else if (b->cols) {
