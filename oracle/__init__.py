@@ -60,25 +60,32 @@ _lib = None
 
 def lib():
     global _lib
+    if _lib is None and os.environ.get("SCG_ORACLE_LIB"):
+        # an explicitly chosen build (the sanitizer build in the tests)
+        _lib = _declare(ctypes.CDLL(os.environ["SCG_ORACLE_LIB"]))
     if _lib is None:
         if not os.path.exists(LIB_PATH) or os.path.getmtime(LIB_PATH) < max(os.path.getmtime(SRC),
                                                                               os.path.getmtime(INC)):
             build()
-        L = ctypes.CDLL(LIB_PATH)
-        P = ctypes.c_void_p
-        i32, i64 = ctypes.c_int32, ctypes.c_int64
-        L.or_dc_table.argtypes = [P, i32, P, i32, i32, P, P]
-        L.or_dc_table.restype = ctypes.c_int
-        L.or_dc_table_wide.argtypes = [P, i32, P, i32, i32, P, P]
-        L.or_dc_table_wide.restype = ctypes.c_int
-        L.or_pattern_masks.argtypes = [P, i32, P]
-        L.or_pattern_masks.restype = ctypes.c_int
-        L.or_align_pair.argtypes = [P, i32, P, i32, i32, i32, i32, P, P, P, i64, P, P, P, i64, P, i32]
-        L.or_align_pair.restype = ctypes.c_int
-        L.or_align_batch.argtypes = [i32, P, P, P, P, i32, i32, i32, i32, P, P, P, P, P, P, P]
-        L.or_align_batch.restype = ctypes.c_int
-        _lib = L
+        _lib = _declare(ctypes.CDLL(LIB_PATH))
     return _lib
+
+
+def _declare(L):
+    """ctypes signatures of the oracle's exported functions."""
+    P = ctypes.c_void_p
+    i32, i64 = ctypes.c_int32, ctypes.c_int64
+    L.or_dc_table.argtypes = [P, i32, P, i32, i32, P, P]
+    L.or_dc_table.restype = ctypes.c_int
+    L.or_dc_table_wide.argtypes = [P, i32, P, i32, i32, P, P]
+    L.or_dc_table_wide.restype = ctypes.c_int
+    L.or_pattern_masks.argtypes = [P, i32, P]
+    L.or_pattern_masks.restype = ctypes.c_int
+    L.or_align_pair.argtypes = [P, i32, P, i32, i32, i32, i32, P, P, P, i64, P, P, P, i64, P, i32]
+    L.or_align_pair.restype = ctypes.c_int
+    L.or_align_batch.argtypes = [i32, P, P, P, P, i32, i32, i32, i32, P, P, P, P, P, P, P]
+    L.or_align_batch.restype = ctypes.c_int
+    return L
 
 
 def _ptr(a: np.ndarray):

@@ -79,3 +79,67 @@ def replay(pattern: bytes, text: bytes, ops) -> tuple[int, int]:
             raise AssertionError(("bad op", op))
     assert j == len(pattern), ("pattern not consumed", j, len(pattern))
     return edits, i
+
+
+# Traceback priority used throughout: match, then substitution, then a pattern
+# character missing from the text (I), then a text character missing from the
+# pattern (D).
+OP_M, OP_S, OP_I, OP_D = 0, 1, 2, 3
+
+
+def dp_traceback(pattern: bytes, text: bytes, d: int, cap: int, D=None):
+    """GenASM-TB restated on the integer table: from (0, 0) at distance d,
+    take the first available of M, S, I, D, where an edge is available when it
+    reaches a cell whose suffix distance is within the remaining budget
+    (Theorem 1: a 0 at bit j of R[i][e] means D(i, j) <= e).  Stops once cap
+    characters of either sequence are consumed or the pattern is used up.
+    Returns (ops, text consumed, pattern consumed, I/D ties met)."""
+    if D is None:
+        D = suffix_dp(pattern, text)
+    m, n = len(pattern), len(text)
+    i = j = ties = 0
+    ops = []
+    while j < m and i < cap and j < cap:
+        has_t = i < n
+        if has_t and text[i] == pattern[j] and D[i + 1][j + 1] <= d:
+            op = OP_M
+        else:
+            s_ok = has_t and d > 0 and D[i + 1][j + 1] <= d - 1
+            i_ok = d > 0 and D[i][j + 1] <= d - 1
+            d_ok = has_t and d > 0 and D[i + 1][j] <= d - 1
+            ties += int(not s_ok and i_ok and d_ok)
+            if s_ok:
+                op = OP_S
+            elif i_ok:
+                op = OP_I
+            elif d_ok:
+                op = OP_D
+            else:
+                raise AssertionError(("no edge", i, j, d))
+        ops.append(op)
+        i += op != OP_I
+        j += op != OP_D
+        d -= op != OP_M
+    return ops, i, j, ties
+
+
+def windowed_dp_align(pattern: bytes, text: bytes, W: int, O: int, k: int):
+    """The windowing of the method with the integer-table traceback above:
+    window at (p0, t0) over at most W characters of each sequence, budget
+    min(k, m_w), advance by what the traceback consumed.  Returns (status,
+    edits, text_end, ops, I/D ties met); status 1 = some window's distance
+    exceeds its budget."""
+    m, n = len(pattern), len(text)
+    p0 = t0 = ties = 0
+    ops = []
+    while p0 < m:
+        pw, tw = pattern[p0:p0 + W], text[t0:t0 + W]
+        D = suffix_dp(pw, tw)
+        if D[0][0] > min(k, len(pw)):
+            return 1, -1, -1, [], ties
+        wops, di, dj, t = dp_traceback(pw, tw, D[0][0], W - O, D)
+        ops += wops
+        ties += t
+        p0 += dj
+        t0 += di
+    return 0, sum(op != OP_M for op in ops), t0, ops, ties

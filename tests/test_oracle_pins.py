@@ -293,3 +293,26 @@ def test_edge_cases():
     # long text tail is free
     r = oracle.align_pair(b"ACGTACGTAC", b"ACGTACGTAC" + b"G" * 200, 64, 24, 64)
     assert (r["edits"], r["text_end"]) == (0, 10)
+
+
+# --- Section 2.2.2: the traceback's edge order, restated on the integer table ---------------
+
+@pytest.mark.parametrize("W,O,length", [(8, 3, 60), (16, 5, 120), (64, 24, 260), (128, 40, 300)])
+def test_traceback_order_matches_integer_table_traceback(W, O, length):
+    """Windowed alignment with an independent traceback over the textbook
+    suffix-distance table (tests/refs.py) gives the oracle's exact op stream.
+    The table traceback takes M, S, I, D in that order, so a swap of any two
+    edges in the oracle changes the path at the first tie; the test checks
+    that ties between I and D (the ones a tight path can meet) occur."""
+    rng = np.random.default_rng(W * 7 + O)
+    ties = 0
+    for case in range(24):
+        p = rand_seq(rng, int(rng.integers(length // 2, length)))
+        t = mutate(rng, p, 0.2) if case % 6 else rand_seq(rng, int(rng.integers(length // 2, length)))
+        st, e, te, ops, tie = refs.windowed_dp_align(p, t, W, O, W)
+        ties += tie
+        r = oracle.align_pair(p, t, W, O, W)
+        assert r["status"] == st == 0
+        assert (r["edits"], r["text_end"]) == (e, te), case
+        assert r["ops"].tolist() == ops, case
+    assert ties > 0
