@@ -18,6 +18,9 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libscrooge_hip.so")
 SOURCES = ["pack.hip", "align.hip", "align_cols.hip", "align_wide.hip", "mlp.hip", "capi.cpp"]
+# the resource microbenchmarks (VALU, LDS, load latency) are a library of their own
+PEAK_LIB = os.path.join(HERE, "libscrooge_peak.so")
+PEAK_SOURCES = ["peak.hip"]
 ARCH = os.environ.get("SCG_OFFLOAD_ARCH", "gfx950")
 
 HIPCC_FLAGS = [
@@ -62,11 +65,18 @@ def register_boundary_problems(asm: str) -> list:
 
 
 def build(verbose: bool = False, jobs: int = 4) -> str:
+    """Compile both libraries; returns the alignment library's path."""
+    _build_one(SOURCES, LIB, verbose, jobs)
+    _build_one(PEAK_SOURCES, PEAK_LIB, verbose, jobs)
+    return LIB
+
+
+def _build_one(sources, lib, verbose: bool, jobs: int) -> str:
     cc = hipcc()
     tmp = tempfile.mkdtemp(prefix="scg_build_")
     try:
         objs, procs, asms = [], [], []
-        for src in SOURCES:
+        for src in sources:
             obj = os.path.join(tmp, src + ".o")
             lang = ["-x", "hip"] if src.endswith(".cpp") else []
             cmds = [[cc, *HIPCC_FLAGS, *lang, "-c", os.path.join(CSRC, src), "-o", obj]]
@@ -93,15 +103,15 @@ def build(verbose: bool = False, jobs: int = 4) -> str:
         problems = [q for a in asms for q in register_boundary_problems(open(a).read())]
         if problems:
             raise RuntimeError("register-boundary check failed:\n" + "\n".join(problems))
-        tmp_lib = LIB + ".tmp"
+        tmp_lib = lib + ".tmp"
         cmd = [cc, f"--offload-arch={ARCH}", "-shared", "-fPIC", *objs, "-o", tmp_lib]
         r = subprocess.run(cmd, stdout=subprocess.PIPE, stderr=subprocess.STDOUT)
         if r.returncode != 0:
             raise RuntimeError("link failed:\n" + r.stdout.decode(errors="replace"))
-        os.replace(tmp_lib, LIB)
+        os.replace(tmp_lib, lib)
     finally:
         shutil.rmtree(tmp, ignore_errors=True)
-    return LIB
+    return lib
 
 
 if __name__ == "__main__":
