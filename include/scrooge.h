@@ -53,7 +53,8 @@ enum {
     SCG_ENOMEM = -4,      /* device or host allocation failed                  */
     SCG_EDEVICE = -5,     /* a HIP runtime call failed                         */
     SCG_ENOMODEL = -6,    /* learned mode requested without a loaded predictor */
-    SCG_EINTERNAL = -7    /* the device reported an inconsistent state         */
+    SCG_EINTERNAL = -7,   /* the device reported an inconsistent state         */
+    SCG_ELIMIT = -8       /* batch larger than the allocation-free workspace   */
 };
 
 /* per-pair status values */
@@ -217,6 +218,44 @@ int scg_align_batch(scg_ctx* ctx, const scg_params* params, int32_t npairs,
                     const void* pat, const int64_t* pat_off, const void* txt, const int64_t* txt_off,
                     int32_t where, void* stream, int32_t* edits, int32_t* text_end, int32_t* status,
                     uint32_t* runs, int32_t* n_runs);
+
+/* ---- allocation-free batch call ----
+ *
+ * For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the same
+ * alignment as scg_align_batch in plain mode (column-block kernel, input
+ * order, W <= 64, no yields, flags 0), with every buffer besides the caller's
+ * inputs and outputs taken from a static device workspace of fixed size that
+ * each device holds for the life of the process (SCG_NOALLOC_DENT_MIB MiB of
+ * stored rows plus planes and per-pair tables for the limits below, about
+ * 105 MB).  The call enqueues its kernels on `stream` and returns without
+ * synchronising; it calls no hipMalloc, hipFree or other allocating routine.
+ *
+ * All pointers are DEVICE pointers: pat/txt ASCII bytes (pat_total and
+ * txt_total bytes, stated by the caller in host ints), pat_off/txt_off
+ * npairs+1 int64 byte offsets each, outputs as for scg_batch_run (edits,
+ * text_end, status, n_runs: npairs int32; runs: sum over pairs of
+ * (m + n + 1) uint32 words, pair p at sum over i < p of (m_i + n_i + 1)).
+ * Offsets out of order or beyond the stated totals make every pair
+ * SCG_PAIR_BAD_INPUT (checked on the device).
+ *
+ * Limits: npairs <= SCG_NOALLOC_MAX_PAIRS, pat_total and txt_total <=
+ * SCG_NOALLOC_MAX_BASES (else SCG_ELIMIT, nothing enqueued); the number of
+ * wavefronts is capped by the stored-row region, so very large batches run
+ * with fewer windows in flight than scg_align_batch would use.
+ * Every call on a device shares that device's workspace and leaves its
+ * contents behind: calls that overlap on one device (different streams or
+ * host threads without ordering) race and must not be issued.
+ * Errors: SCG_EINVAL, SCG_ELIMIT, SCG_EDEVICE. */
+enum {
+    SCG_NOALLOC_MAX_PAIRS = 65536,
+    SCG_NOALLOC_MAX_BASES = 67108864,
+    SCG_NOALLOC_DENT_MIB = 64
+};
+int scg_align_batch_noalloc(scg_ctx* ctx, const scg_params* params, int32_t npairs,
+                            const void* pat, const int64_t* pat_off, int64_t pat_total,
+                            const void* txt, const int64_t* txt_off, int64_t txt_total, void* stream,
+                            int32_t* edits, int32_t* text_end, int32_t* status, uint32_t* runs, int32_t* n_runs);
 
 /* Counters and timings of the context's last scg_align_batch (zeros before
  * the first).  Errors: SCG_EINVAL. */

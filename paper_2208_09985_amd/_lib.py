@@ -11,7 +11,8 @@ import os
 HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libscrooge_hip.so")
 
-OK, EINVAL, EALPHABET, ERANGE, ENOMEM, EDEVICE, ENOMODEL, EINTERNAL = 0, -1, -2, -3, -4, -5, -6, -7
+OK, EINVAL, EALPHABET, ERANGE, ENOMEM, EDEVICE, ENOMODEL, EINTERNAL, ELIMIT = 0, -1, -2, -3, -4, -5, -6, -7, -8
+NOALLOC_MAX_PAIRS, NOALLOC_MAX_BASES = 65536, 67108864
 PAIR_OK, PAIR_NOT_ALIGNED, PAIR_BAD_INPUT, PAIR_ERROR = 0, 1, 2, 3
 MODE_PLAIN, MODE_LEARNED, MODE_FIXED = 0, 1, 2
 ORDER_INPUT, ORDER_LONGEST_FIRST = 0, 1
@@ -27,7 +28,7 @@ EXPORTED = [
     "scg_batch_create", "scg_batch_destroy", "scg_batch_runs_capacity", "scg_batch_runs_offsets",
     "scg_batch_run", "scg_batch_stats", "scg_align", "scg_align_batch", "scg_last_stats", "scg_runs_to_cigar",
     "scg_features",
-    "scg_mlp_forward", "scg_mlp_backward", "scg_adam_step",
+    "scg_mlp_forward", "scg_mlp_backward", "scg_adam_step", "scg_align_batch_noalloc",
 ]
 
 
@@ -88,6 +89,8 @@ def load():
         "scg_batch_stats": ([P, ctypes.POINTER(Stats)], ctypes.c_int),
         "scg_align_batch": ([P, ctypes.POINTER(Params), i32, P, P, P, P, i32, P, P, P, P, P, P], ctypes.c_int),
         "scg_last_stats": ([P, ctypes.POINTER(Stats)], ctypes.c_int),
+        "scg_align_batch_noalloc": ([P, ctypes.POINTER(Params), i32, P, P, i64, P, P, i64, P, P, P, P, P, P],
+                                    ctypes.c_int),
         "scg_align": ([P, ctypes.c_char_p, i32, ctypes.c_char_p, i32, i32, i32, i32, P, P, ctypes.c_char_p, i32, P],
                       ctypes.c_int),
         "scg_runs_to_cigar": ([P, i32, ctypes.c_char_p, i32, P], ctypes.c_int),

@@ -254,3 +254,32 @@ def align_batch_once(ctx: Context, batch, W=64, O=24, k=64, mode="plain", host=T
     res.runs = np.asarray(res.runs).view(np.uint32)
     res.stats = st
     return res
+
+
+def align_batch_noalloc(ctx: Context, batch, W=64, O=24, k=64, stream=None, **kw) -> Result:
+    """scg_align_batch_noalloc: device arrays in and out, the library's static
+    workspace instead of allocations.  Returns host results."""
+    import torch
+    prm = params(W=W, O=O, k=k, mode="plain", **kw)
+    n = int(len(batch.pat_off) - 1)
+    dev = torch.device(f"cuda:{ctx.device}")
+    pat_off = np.ascontiguousarray(batch.pat_off, dtype=np.int64)
+    txt_off = np.ascontiguousarray(batch.txt_off, dtype=np.int64)
+    lens = (pat_off[1:] - pat_off[:-1]) + (txt_off[1:] - txt_off[:-1]) + 1
+    runs_off = np.zeros(n + 1, np.int64)
+    np.cumsum(lens, out=runs_off[1:])
+    pat = torch.from_numpy(np.ascontiguousarray(batch.pat)).to(dev)
+    txt = torch.from_numpy(np.ascontiguousarray(batch.txt)).to(dev)
+    po = torch.from_numpy(pat_off).to(dev)
+    to = torch.from_numpy(txt_off).to(dev)
+    outs = [torch.full((max(n, 1),), -9, dtype=torch.int32, device=dev) for _ in range(4)]
+    runs = torch.zeros(max(int(runs_off[-1]), 1), dtype=torch.int32, device=dev)
+    torch.cuda.synchronize(dev)
+    rc = ctx._lib.scg_align_batch_noalloc(ctx.handle, ctypes.byref(prm), n, _ptr(pat), _ptr(po), int(pat_off[-1]),
+                                          _ptr(txt), _ptr(to), int(txt_off[-1]), _stream_ptr(stream), _ptr(outs[0]),
+                                          _ptr(outs[1]), _ptr(outs[2]), _ptr(runs), _ptr(outs[3]))
+    L.check(rc, "scg_align_batch_noalloc")
+    torch.cuda.synchronize(dev)
+    res = Result(outs[0][:n], outs[1][:n], outs[2][:n], runs, outs[3][:n], runs_off).to_host()
+    res.runs = np.asarray(res.runs).view(np.uint32)
+    return res

@@ -221,6 +221,11 @@ int enqueue_run(scg_batch* b, hipStream_t s, int32_t* edits, int32_t* text_end, 
 
 }  // namespace
 
+// helpers for the allocation-free entry point (noalloc.hip)
+int capi_check_params(const scg_params* p) { return check_params(p); }
+int capi_from_hip(hipError_t e, const char* what) { return from_hip(e, what); }
+int capi_ctx_device(const scg_ctx* c) { return c->device; }
+
 extern "C" {
 
 const char* scg_strerror(int code) {
@@ -233,6 +238,7 @@ const char* scg_strerror(int code) {
     case SCG_EDEVICE: return "HIP runtime error";
     case SCG_ENOMODEL: return "no predictor loaded";
     case SCG_EINTERNAL: return "internal inconsistency";
+    case SCG_ELIMIT: return "batch exceeds the allocation-free workspace";
     default: return "unknown status";
     }
 }
@@ -265,6 +271,9 @@ int scg_create(scg_ctx** out, int device) {
     if (!c) return SCG_ENOMEM;
     c->device = device;
     c->num_cu = prop.multiProcessorCount;
+    // device address of the allocation-free workspace (looked up once per
+    // device; a failure here is reported by scg_align_batch_noalloc itself)
+    (void)noalloc_init(device);
     *out = c;
     return SCG_OK;
 }

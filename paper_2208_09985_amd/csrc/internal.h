@@ -104,5 +104,6 @@ hipError_t launch_mlp_forward(int32_t B, int32_t F, int32_t H, int32_t C, const 
 hipError_t launch_mlp_backward(int32_t B, int32_t F, int32_t H, int32_t C, const __half* x,
                                const __half* hidden, const __half* w2, const float* dlogits, float* gw1,
                                float* gb1, float* gw2, float* gb2, hipStream_t s);
+int noalloc_init(int device);   // noalloc.hip: device address of its static workspace
 hipError_t launch_adam(int32_t n, float* p, const float* g, float* m, float* v, __half* p16, float lr,
                        float b1, float b2, float eps, int32_t step, hipStream_t s);
