@@ -77,6 +77,14 @@ enum {
 
 enum { SCG_ORDER_INPUT = 0, SCG_ORDER_LONGEST_FIRST = 1 };
 enum { SCG_WHERE_HOST = 0, SCG_WHERE_DEVICE = 1 };
+/* input_kind of the batch calls: how pattern and text bytes are encoded */
+enum {
+    SCG_INPUT_ASCII = 0,   /* one ASCII byte per base (A/C/G/T, either case); offsets count bytes    */
+    SCG_INPUT_PACKED2 = 1  /* two bits per base (the paper's 2-bit encoding, Section 2.5): 32 bases */
+                           /* per uint64, base t of a word in bits 2t and 2t+1; offsets count bases; */
+                           /* sequence i starts at uint64 word sum over j < i of ceil(len_j / 32).   */
+                           /* Any code assignment works as long as patterns and texts share it       */
+};
 enum {
     SCG_FLAG_GRAPH = 1,              /* replay the batch's launches from a captured hipGraph   */
     /* Ablations of the paper's improvements (Section 2.4), plain mode in the column-block     */
@@ -98,8 +106,9 @@ typedef struct {
     int32_t W, O, k;        /* window size, overlap, edit budget per window            */
     int32_t mode;           /* SCG_MODE_*                                              */
     int32_t slots;          /* windows in flight per wavefront, 1..16 (0 = automatic); */
-                            /* column blocks round up to 4, 8, 16 or (plain and fixed  */
-                            /* modes, slots 17..32) 32                                 */
+                            /* column blocks round up to 4, 8, 16 or, in plain and     */
+                            /* fixed modes, 10 (slots 9..10: six lanes of 12 columns)  */
+                            /* or 32 (slots 17..32)                                    */
     int32_t waves_per_cu;   /* persistent wavefronts per CU (0 = occupancy maximum)    */
     int32_t order;          /* SCG_ORDER_* : queue order of pairs                      */
     int32_t fixed_rows;     /* SCG_MODE_FIXED: rows computed before falling back       */
@@ -145,8 +154,13 @@ const char* scg_last_hip_error(void);
 void scg_params_default(scg_params* p);
 
 /* Create a context on HIP device `device`.  *out receives the context; the
- * caller releases it with scg_destroy.  Errors: SCG_EINVAL, SCG_EDEVICE. */
-int scg_create(scg_ctx** out, int device);
+ * caller releases it with scg_destroy.  weights_path names a predictor file
+ * for SCG_MODE_LEARNED (NULL: plain and fixed modes only, or a later
+ * scg_set_model).  The file is little-endian: the bytes "SCGW", uint32
+ * version 1, int32 F, H, C, int32 budget_rows[C], then FP16 w1[F*H], b1[H],
+ * w2[H*C], b2[C] (as scg_set_model), nothing after.
+ * Errors: SCG_EINVAL (also a missing or malformed file), SCG_EDEVICE. */
+int scg_create(scg_ctx** out, int device, const char* weights_path);
 void scg_destroy(scg_ctx* ctx);
 
 /* Number of compute units of the context's device (for launch planning). */
@@ -156,7 +170,7 @@ int scg_device_cus(const scg_ctx* ctx);
  * F -> H (ReLU) -> C over per-window features (scg_features), all FP16,
  * host arrays, row-major: w1[F*H], b1[H], w2[H*C], b2[C].  Class c predicts
  * "d_w fits in budget_rows[c] rows" (budget_rows: C increasing int32,
- * the last >= 64).  F must be SCG_NFEATURES, H <= 64, C <= 16.
+ * the last >= 64).  F must be SCG_NFEATURES, H <= 64, C <= 4.
  * Copied to the device; the host arrays stay the caller's. */
 enum { SCG_NFEATURES = 16 };
 int scg_set_model(scg_ctx* ctx, int32_t F, int32_t H, int32_t C,
@@ -164,8 +178,9 @@ int scg_set_model(scg_ctx* ctx, int32_t F, int32_t H, int32_t C,
                   const int32_t* budget_rows);
 
 /* Prepare a batch of npairs (pattern, text) pairs for repeated alignment.
- * pat/txt: concatenated ASCII bytes; pat_off/txt_off: npairs+1 int64 byte
- * offsets, always in HOST memory.  where = SCG_WHERE_HOST (bytes in host
+ * pat/txt: concatenated sequences encoded as input_kind says (SCG_INPUT_*);
+ * pat_off/txt_off: npairs+1 int64 offsets (bytes for ASCII, bases for packed
+ * input), always in HOST memory.  where = SCG_WHERE_HOST (bytes in host
  * memory, validated and copied to the device) or SCG_WHERE_DEVICE (bytes
  * already in device memory, used in place: they must outlive the batch).
  * The batch owns its workspace (2-bit planes, queue, counters); free it
@@ -173,7 +188,7 @@ int scg_set_model(scg_ctx* ctx, int32_t F, int32_t H, int32_t C,
  * SCG_EDEVICE, SCG_ENOMODEL (learned mode without scg_set_model). */
 int scg_batch_create(scg_ctx* ctx, const scg_params* params, int32_t npairs,
                      const void* pat, const int64_t* pat_off, const void* txt, const int64_t* txt_off,
-                     int32_t where, void* stream, scg_batch** out);
+                     int32_t input_kind, int32_t where, void* stream, scg_batch** out);
 void scg_batch_destroy(scg_batch* b);
 
 /* uint32 words the runs buffer of scg_batch_run needs, and the per-pair
@@ -204,27 +219,39 @@ int scg_align(scg_ctx* ctx, const char* pattern, int32_t m, const char* text, in
               char* cigar, int32_t cigar_cap, int32_t* cigar_len);
 
 /* A whole batch in one call (the align-all call of supplementary Section 7,
- * tool function calls): scg_batch_create + scg_batch_run + synchronise +
- * destroy.
+ * tool function calls; the problem statement of Section 2.1 per pair: edit
+ * count and edit sequence): scg_batch_create + scg_batch_run + expansion of
+ * the runs into operation streams + synchronise + destroy.
  * Inputs as in scg_batch_create.  Outputs live where the inputs do: with
  * SCG_WHERE_HOST they are host arrays (the library allocates device
  * buffers for the run and copies back), with SCG_WHERE_DEVICE device arrays
- * written in place.  edits, text_end, status, n_runs: npairs int32 each;
- * runs: sum over pairs of (m + n + 1) uint32 words, pair p starting at
- * sum over i < p of (m_i + n_i + 1).  Returns when the outputs are complete.
- * The counters and timings of the run are kept for scg_last_stats.
- * Errors: as scg_batch_create and scg_batch_run. */
+ * written in place.  edits, text_end, status, n_ops: npairs int32 each.
+ * ops: each pair's operations at two bits each (SCG_OP_*), operation t of
+ * pair p in byte ops_off[p] + t / 4, bits 2 (t % 4) and 2 (t % 4) + 1;
+ * ops_off: npairs+1 int64 byte offsets, always in HOST memory; pair p needs
+ * ceil((m_p + n_p) / 4) bytes (SCG_ERANGE otherwise, nothing run);
+ * n_ops[p] operations are written (0 for pairs with status != SCG_PAIR_OK).
+ * Returns when the outputs are complete.  The counters and timings of the
+ * run are kept for scg_last_stats.
+ * Errors: as scg_batch_create and scg_batch_run, and SCG_ERANGE. */
 int scg_align_batch(scg_ctx* ctx, const scg_params* params, int32_t npairs,
                     const void* pat, const int64_t* pat_off, const void* txt, const int64_t* txt_off,
-                    int32_t where, void* stream, int32_t* edits, int32_t* text_end, int32_t* status,
-                    uint32_t* runs, int32_t* n_runs);
+                    int32_t input_kind, int32_t where, void* stream,
+                    int32_t* edits, int32_t* text_end, int32_t* status,
+                    uint8_t* ops, const int64_t* ops_off, int32_t* n_ops);
+
+/* Render a 2-bit operation stream (as written by scg_align_batch) as a
+ * NUL-terminated CIGAR string, runs of equal operations merged ("12=1X3I");
+ * cap must cover it (SCG_ERANGE with *len = needed length otherwise). */
+int scg_ops_to_cigar(const uint8_t* ops, int32_t n_ops, char* cigar, int32_t cap, int32_t* len);
 
 /* ---- allocation-free batch call ----
  *
  * For callers that cannot allocate device memory (code under HIP graph
  * capture, tight serving loops, harnesses that forbid hipMalloc): the same
- * alignment as scg_align_batch in plain mode (column-block kernel, input
- * order, W <= 64, no yields, flags 0), with every buffer besides the caller's
+ * alignment and run-word output as scg_batch_create + scg_batch_run in plain
+ * mode (column-block kernel, input order, W <= 64, no yields, flags 0) on
+ * device input, in one call, with every buffer besides the caller's
  * inputs and outputs taken from a static device workspace of fixed size that
  * each device holds for the life of the process (SCG_NOALLOC_DENT_MIB MiB of
  * stored rows plus planes and per-pair tables for the limits below, about
@@ -258,8 +285,13 @@ int scg_align_batch_noalloc(scg_ctx* ctx, const scg_params* params, int32_t npai
                             int32_t* edits, int32_t* text_end, int32_t* status, uint32_t* runs, int32_t* n_runs);
 
 /* Counters and timings of the context's last scg_align_batch (zeros before
- * the first).  Errors: SCG_EINVAL. */
-int scg_last_stats(const scg_ctx* ctx, scg_stats* out);
+ * the first): its alignment kernel time, its algorithmic work (sum over
+ * windows of (d_w+1) + 2 n_w + 7 n_w d_w, supplementary Section 8's work
+ * model) and the windows recomputed after missing a row budget.  Any output
+ * pointer may be NULL.  scg_last_stats_all returns every counter.
+ * Errors: SCG_EINVAL. */
+int scg_last_stats(const scg_ctx* ctx, double* kernel_ms, int64_t* ops_alg, int64_t* fallback_windows);
+int scg_last_stats_all(const scg_ctx* ctx, scg_stats* out);
 
 /* Render run words as a CIGAR string (host memory). */
 int scg_runs_to_cigar(const uint32_t* runs, int32_t n_runs, char* cigar, int32_t cap, int32_t* len);
@@ -286,10 +318,15 @@ int scg_mlp_forward(int32_t B, int32_t F, int32_t H, int32_t C, const uint16_t* 
                     void* stream);
 
 /* Backward pass: given x, hidden (from forward), w2 and dlogits, accumulate
- * FP32 gradients gw1[F*H], gb1[H], gw2[H*C], gb2[C] (overwritten, not added). */
+ * FP32 gradients gw1[F*H], gb1[H], gw2[H*C], gb2[C] (overwritten, not added).
+ * workspace: a caller-owned device buffer of at least
+ * scg_mlp_backward_workspace(B, H, C) floats for the per-block partial sums
+ * (SCG_ERANGE if smaller); calls that share one workspace must not overlap. */
+int64_t scg_mlp_backward_workspace(int32_t B, int32_t H, int32_t C);
 int scg_mlp_backward(int32_t B, int32_t F, int32_t H, int32_t C, const uint16_t* x, const uint16_t* hidden,
                      const uint16_t* w2, const float* dlogits,
-                     float* gw1, float* gb1, float* gw2, float* gb2, void* stream);
+                     float* gw1, float* gb1, float* gw2, float* gb2,
+                     float* workspace, int64_t workspace_floats, void* stream);
 
 /* Adam step on FP32 master weights p[n] with gradient g[n] and moments m, v
  * (all device), writing the FP16 copy p16[n].  step is 1-based. */

@@ -17,6 +17,7 @@ PAIR_OK, PAIR_NOT_ALIGNED, PAIR_BAD_INPUT, PAIR_ERROR = 0, 1, 2, 3
 MODE_PLAIN, MODE_LEARNED, MODE_FIXED = 0, 1, 2
 ORDER_INPUT, ORDER_LONGEST_FIRST = 0, 1
 WHERE_HOST, WHERE_DEVICE = 0, 1
+INPUT_ASCII, INPUT_PACKED2 = 0, 1
 FLAG_GRAPH = 1
 FLAG_NO_EARLY_TERMINATION = 2
 FLAG_STORE_ALL_COLUMNS = 4
@@ -26,9 +27,11 @@ NFEATURES = 16
 EXPORTED = [
     "scg_strerror", "scg_last_hip_error", "scg_params_default", "scg_create", "scg_destroy", "scg_device_cus", "scg_set_model",
     "scg_batch_create", "scg_batch_destroy", "scg_batch_runs_capacity", "scg_batch_runs_offsets",
-    "scg_batch_run", "scg_batch_stats", "scg_align", "scg_align_batch", "scg_last_stats", "scg_runs_to_cigar",
+    "scg_batch_run", "scg_batch_stats", "scg_align", "scg_align_batch", "scg_last_stats", "scg_last_stats_all",
+    "scg_runs_to_cigar", "scg_ops_to_cigar",
     "scg_features",
-    "scg_mlp_forward", "scg_mlp_backward", "scg_adam_step", "scg_align_batch_noalloc",
+    "scg_mlp_forward", "scg_mlp_backward", "scg_mlp_backward_workspace", "scg_adam_step",
+    "scg_align_batch_noalloc",
 ]
 
 
@@ -77,18 +80,20 @@ def load():
         "scg_strerror": ([ctypes.c_int], ctypes.c_char_p),
         "scg_last_hip_error": ([], ctypes.c_char_p),
         "scg_params_default": ([ctypes.POINTER(Params)], None),
-        "scg_create": ([pp, ctypes.c_int], ctypes.c_int),
+        "scg_create": ([pp, ctypes.c_int, ctypes.c_char_p], ctypes.c_int),
         "scg_destroy": ([P], None),
         "scg_device_cus": ([P], ctypes.c_int),
         "scg_set_model": ([P, i32, i32, i32, P, P, P, P, P], ctypes.c_int),
-        "scg_batch_create": ([P, ctypes.POINTER(Params), i32, P, P, P, P, i32, P, pp], ctypes.c_int),
+        "scg_batch_create": ([P, ctypes.POINTER(Params), i32, P, P, P, P, i32, i32, P, pp], ctypes.c_int),
         "scg_batch_destroy": ([P], None),
         "scg_batch_runs_capacity": ([P], i64),
         "scg_batch_runs_offsets": ([P, P], ctypes.c_int),
         "scg_batch_run": ([P, P, P, P, P, P, P], ctypes.c_int),
         "scg_batch_stats": ([P, ctypes.POINTER(Stats)], ctypes.c_int),
-        "scg_align_batch": ([P, ctypes.POINTER(Params), i32, P, P, P, P, i32, P, P, P, P, P, P], ctypes.c_int),
-        "scg_last_stats": ([P, ctypes.POINTER(Stats)], ctypes.c_int),
+        "scg_align_batch": ([P, ctypes.POINTER(Params), i32, P, P, P, P, i32, i32, P, P, P, P, P, P, P], ctypes.c_int),
+        "scg_last_stats": ([P, P, P, P], ctypes.c_int),
+        "scg_last_stats_all": ([P, ctypes.POINTER(Stats)], ctypes.c_int),
+        "scg_ops_to_cigar": ([P, i32, ctypes.c_char_p, i32, P], ctypes.c_int),
         "scg_align_batch_noalloc": ([P, ctypes.POINTER(Params), i32, P, P, i64, P, P, i64, P, P, P, P, P, P],
                                     ctypes.c_int),
         "scg_align": ([P, ctypes.c_char_p, i32, ctypes.c_char_p, i32, i32, i32, i32, P, P, ctypes.c_char_p, i32, P],
@@ -96,7 +101,8 @@ def load():
         "scg_runs_to_cigar": ([P, i32, ctypes.c_char_p, i32, P], ctypes.c_int),
         "scg_features": ([P, i32, P, P, P], ctypes.c_int),
         "scg_mlp_forward": ([i32, i32, i32, i32, P, P, P, P, P, P, P, P, P, P, P], ctypes.c_int),
-        "scg_mlp_backward": ([i32, i32, i32, i32, P, P, P, P, P, P, P, P, P], ctypes.c_int),
+        "scg_mlp_backward": ([i32, i32, i32, i32, P, P, P, P, P, P, P, P, P, i64, P], ctypes.c_int),
+        "scg_mlp_backward_workspace": ([i32, i32, i32], i64),
         "scg_adam_step": ([i32, P, P, P, P, P, f32, f32, f32, f32, i32, P], ctypes.c_int),
     }
     for name, (args, res) in sig.items():

@@ -56,10 +56,11 @@ def params(W=64, O=24, k=64, mode="plain", slots=0, waves_per_cu=0, order="input
 class Context:
     """A device context (scg_create).  Holds the learned predictor, if any."""
 
-    def __init__(self, device: int = 0):
+    def __init__(self, device: int = 0, weights_path: str | None = None):
         self._lib = L.load()
         h = ctypes.c_void_p()
-        L.check(self._lib.scg_create(ctypes.byref(h), device), "scg_create")
+        wp = None if weights_path is None else os.fsencode(weights_path)
+        L.check(self._lib.scg_create(ctypes.byref(h), device, wp), "scg_create")
         self.handle = h
         self.device = device
 
@@ -133,7 +134,8 @@ class Result:
 class Batch:
     """A prepared batch (scg_batch_create) and its output buffers."""
 
-    def __init__(self, ctx: Context, batch, prm: L.Params | None = None, device_input: bool = True, stream=None):
+    def __init__(self, ctx: Context, batch, prm: L.Params | None = None, device_input: bool = True, stream=None,
+                 packed: bool = False):
         import torch
         self.ctx = ctx
         self._lib = ctx._lib
@@ -143,20 +145,24 @@ class Batch:
         pat_off = np.ascontiguousarray(batch.pat_off, dtype=np.int64)
         txt_off = np.ascontiguousarray(batch.txt_off, dtype=np.int64)
         self._keep = [pat_off, txt_off]
+        pat_in, txt_in = batch.pat, batch.txt
+        if packed:
+            pat_in, txt_in = pack2(batch.pat, pat_off), pack2(batch.txt, txt_off)
         if device_input:
-            pat = torch.from_numpy(np.ascontiguousarray(batch.pat)).to(self.dev)
-            txt = torch.from_numpy(np.ascontiguousarray(batch.txt)).to(self.dev)
+            pat = torch.from_numpy(np.ascontiguousarray(pat_in)).to(self.dev)
+            txt = torch.from_numpy(np.ascontiguousarray(txt_in)).to(self.dev)
             torch.cuda.synchronize(self.dev)
             self._keep += [pat, txt]
             where = L.WHERE_DEVICE
         else:
-            pat = np.ascontiguousarray(batch.pat)
-            txt = np.ascontiguousarray(batch.txt)
+            pat = np.ascontiguousarray(pat_in)
+            txt = np.ascontiguousarray(txt_in)
             self._keep += [pat, txt]
             where = L.WHERE_HOST
         h = ctypes.c_void_p()
+        kind = L.INPUT_PACKED2 if packed else L.INPUT_ASCII
         rc = self._lib.scg_batch_create(ctx.handle, ctypes.byref(self.prm), self.npairs, _ptr(pat), _ptr(pat_off),
-                                        _ptr(txt), _ptr(txt_off), where, _stream_ptr(stream), ctypes.byref(h))
+                                        _ptr(txt), _ptr(txt_off), kind, where, _stream_ptr(stream), ctypes.byref(h))
         L.check(rc, "scg_batch_create")
         self.handle = h
         cap = int(self._lib.scg_batch_runs_capacity(h))
@@ -218,40 +224,104 @@ def align_batch(ctx: Context, batch, W=64, O=24, k=64, mode="plain", **kw) -> Re
     return res
 
 
-def align_batch_once(ctx: Context, batch, W=64, O=24, k=64, mode="plain", host=True, **kw) -> Result:
+def pack2(seq: np.ndarray, off: np.ndarray) -> np.ndarray:
+    """ASCII CSR sequences -> the library's pre-packed input form
+    (SCG_INPUT_PACKED2): two bits per base, 32 bases per uint64 (base t in
+    bits 2t, 2t+1), every sequence from a word boundary.  Codes A0 C1 G2 T3.
+    Input preparation only: the library converts it to its own layout."""
+    seq = np.asarray(seq, dtype=np.uint8)
+    lens = np.diff(np.asarray(off, dtype=np.int64))
+    words = (lens + 31) // 32
+    wo = np.zeros(len(lens) + 1, np.int64)
+    np.cumsum(words, out=wo[1:])
+    lut = np.zeros(256, np.uint64)
+    for ch, c in ((b"A", 0), (b"C", 1), (b"G", 2), (b"T", 3)):
+        lut[ch[0]] = c
+        lut[ch.lower()[0]] = c
+    codes = lut[seq]
+    # position of every base in the padded word stream
+    first = np.repeat(wo[:-1] * 32 - np.asarray(off[:-1], np.int64), lens)
+    pos = np.arange(seq.size, dtype=np.int64) + first
+    out = np.zeros(max(int(wo[-1]), 1), np.uint64)
+    np.bitwise_or.at(out, pos // 32, codes << (2 * (pos % 32)).astype(np.uint64))
+    return out[:max(int(wo[-1]), 1)]
+
+
+@dataclasses.dataclass
+class OpsResult:
+    """Output of scg_align_batch: per-pair 2-bit operation streams."""
+    edits: np.ndarray
+    text_end: np.ndarray
+    status: np.ndarray
+    ops: np.ndarray       # uint8, op t of pair p in byte ops_off[p] + t // 4, bits 2 (t % 4) ..
+    ops_off: np.ndarray
+    n_ops: np.ndarray
+
+    def ops_of(self, i: int) -> np.ndarray:
+        """Expanded op list (0..3) of pair i."""
+        n = int(self.n_ops[i])
+        b = self.ops[int(self.ops_off[i]):int(self.ops_off[i]) + (n + 3) // 4]
+        x = np.stack([(b >> (2 * e)) & 3 for e in range(4)], axis=1).reshape(-1)
+        return x[:n].astype(np.uint8)
+
+    def cigar(self, i: int, lib=None) -> str:
+        """scg_ops_to_cigar of pair i."""
+        lib = lib or L.load()
+        n = int(self.n_ops[i])
+        b = np.ascontiguousarray(self.ops[int(self.ops_off[i]):int(self.ops_off[i]) + (n + 3) // 4 + 1])
+        cap = 11 * n + 16
+        buf = ctypes.create_string_buffer(cap)
+        ln = ctypes.c_int32()
+        L.check(lib.scg_ops_to_cigar(_ptr(b), n, buf, cap, ctypes.byref(ln)), "scg_ops_to_cigar")
+        return buf.value.decode()
+
+
+def ops_offsets(batch) -> np.ndarray:
+    """Byte offsets of the per-pair op streams: ceil((m + n) / 4) bytes each."""
+    lens = np.diff(np.asarray(batch.pat_off, np.int64)) + np.diff(np.asarray(batch.txt_off, np.int64))
+    off = np.zeros(len(lens) + 1, np.int64)
+    np.cumsum((lens + 3) // 4, out=off[1:])
+    return off
+
+
+def align_batch_once(ctx: Context, batch, W=64, O=24, k=64, mode="plain", host=True, packed=False,
+                     **kw) -> OpsResult:
     """One scg_align_batch call: host arrays in and out (host=True), or device
-    tensors in and out (host=False).  Returns host results with .stats."""
+    tensors in and out (host=False); ASCII or pre-packed input.  Returns host
+    results with .stats (scg_last_stats_all)."""
     import torch
     prm = params(W=W, O=O, k=k, mode=mode, **kw)
     n = int(len(batch.pat_off) - 1)
     pat_off = np.ascontiguousarray(batch.pat_off, dtype=np.int64)
     txt_off = np.ascontiguousarray(batch.txt_off, dtype=np.int64)
-    lens = (pat_off[1:] - pat_off[:-1]) + (txt_off[1:] - txt_off[:-1]) + 1
-    runs_off = np.zeros(n + 1, np.int64)
-    np.cumsum(lens, out=runs_off[1:])
-    cap = max(int(runs_off[-1]), 1)
+    ops_off = ops_offsets(batch)
+    nbytes = max(int(ops_off[-1]), 1)
+    pat_in, txt_in = (pack2(batch.pat, pat_off), pack2(batch.txt, txt_off)) if packed else (batch.pat, batch.txt)
     lib = ctx._lib
     if host:
-        pat, txt = np.ascontiguousarray(batch.pat), np.ascontiguousarray(batch.txt)
+        pat, txt = np.ascontiguousarray(pat_in), np.ascontiguousarray(txt_in)
         outs = [np.zeros(max(n, 1), np.int32) for _ in range(4)]
-        runs = np.zeros(cap, np.uint32)
-        where, stream = L.WHERE_HOST, None
+        ops = np.zeros(nbytes, np.uint8)
+        where = L.WHERE_HOST
     else:
         dev = torch.device(f"cuda:{ctx.device}")
-        pat = torch.from_numpy(np.ascontiguousarray(batch.pat)).to(dev)
-        txt = torch.from_numpy(np.ascontiguousarray(batch.txt)).to(dev)
+        pat = torch.from_numpy(np.ascontiguousarray(pat_in)).to(dev)
+        txt = torch.from_numpy(np.ascontiguousarray(txt_in)).to(dev)
         outs = [torch.zeros(max(n, 1), dtype=torch.int32, device=dev) for _ in range(4)]
-        runs = torch.zeros(cap, dtype=torch.int32, device=dev)
+        ops = torch.zeros(nbytes, dtype=torch.uint8, device=dev)
         torch.cuda.synchronize(dev)
-        where, stream = L.WHERE_DEVICE, None
+        where = L.WHERE_DEVICE
+    kind = L.INPUT_PACKED2 if packed else L.INPUT_ASCII
     rc = lib.scg_align_batch(ctx.handle, ctypes.byref(prm), n, _ptr(pat), _ptr(pat_off), _ptr(txt), _ptr(txt_off),
-                             where, _stream_ptr(stream), _ptr(outs[0]), _ptr(outs[1]), _ptr(outs[2]), _ptr(runs),
-                             _ptr(outs[3]))
+                             kind, where, _stream_ptr(None), _ptr(outs[0]), _ptr(outs[1]), _ptr(outs[2]), _ptr(ops),
+                             _ptr(ops_off), _ptr(outs[3]))
     L.check(rc, "scg_align_batch")
     st = L.Stats()
-    L.check(lib.scg_last_stats(ctx.handle, ctypes.byref(st)), "scg_last_stats")
-    res = Result(outs[0][:n], outs[1][:n], outs[2][:n], runs, outs[3][:n], runs_off).to_host()
-    res.runs = np.asarray(res.runs).view(np.uint32)
+    L.check(lib.scg_last_stats_all(ctx.handle, ctypes.byref(st)), "scg_last_stats_all")
+
+    def h(x):
+        return x.cpu().numpy() if hasattr(x, "cpu") else x
+    res = OpsResult(h(outs[0])[:n], h(outs[1])[:n], h(outs[2])[:n], h(ops), ops_off, h(outs[3])[:n])
     res.stats = st
     return res
 

@@ -32,7 +32,7 @@ from . import api
 DEFAULT_CACHE = os.path.join(os.path.expanduser("~"), ".cache", "scrooge_mi355x", "autotune.json")
 
 SPACE = {
-    "plain": {"kernel": ["columns"], "slots": [4, 8, 16], "waves_per_cu": [0], "order": ["input", "longest_first"]},
+    "plain": {"kernel": ["columns"], "slots": [4, 8, 10, 16], "waves_per_cu": [0], "order": ["input", "longest_first"]},
     "fixed": {"kernel": ["rows"], "slots": [2, 4, 6, 8], "waves_per_cu": [0], "order": ["input"],
               "fixed_rows": [7, 11, 15, 23]},
     "learned": {"kernel": ["rows"], "slots": [2, 4, 6], "waves_per_cu": [0], "order": ["input"],

@@ -86,15 +86,18 @@ struct GroupRec {      // LDS: what the slot lane tells its group at set-up
 // ST: the stored entries.  0: whole 64-bit entries.  1 (NARROW): their low 32
 // bits, when traceback reads bits 0..31 at most.  2 (SPLIT): their low 48 bits
 // as a 32-bit plane and a 16-bit plane, when it reads bits 0..47 at most.
-template <bool LEARNED, int CB, int ST>
+template <bool LEARNED, int NG, int ST>
 __global__ __launch_bounds__(64) void cols_kernel(const AlignArgs a) {
     constexpr bool NARROW = ST == 1, SPLIT = ST == 2;
-    constexpr int NG = CB;          // windows per wavefront
-    constexpr int L = 64 / NG;      // lanes per window
-    __shared__ GroupRec grec[NG];
+    constexpr int L = 64 / NG;             // lanes per window
+    constexpr int CB = cols_per_lane(NG);  // text columns per lane (CB * L >= 64)
+    // NG * L < 64 (10 windows of 6 lanes): the lanes past the last group hold
+    // no window; they read an always-empty record and never take a pair
+    __shared__ GroupRec grec[NG + 1];
     const int lane = threadIdx.x;
     const int g = lane / L, q = lane % L;
-    const bool slot = q == 0;
+    const bool live = g < NG;
+    const bool slot = live && q == 0;
     const uint64_t gbit = 1ull << (lane - q);   // the group's slot lane in a ballot
     const int cap = a.cap;
     const int stride = a.dstride;
@@ -112,7 +115,7 @@ __global__ __launch_bounds__(64) void cols_kernel(const AlignArgs a) {
     const uint32_t hiplane = gbyte + (uint32_t)kStoredRows * lobytes;
     const bool storer = CB * q < stride;
 
-    if (lane < NG) grec[lane] = GroupRec{0, 0, 0, 0, 0, 0, 0, 0, CMD_NONE, 0};
+    if (lane <= NG) grec[lane] = GroupRec{0, 0, 0, 0, 0, 0, 0, 0, CMD_NONE, 0};
 
     // ---- slot-lane state (lanes with q == 0) ----
     int pair = -1, p0 = 0, t0 = 0, m = 0, n = 0, edits = 0, nruns = 0, cur_op = 0, cur_len = 0, p0_take = 0;
@@ -246,7 +249,8 @@ __global__ __launch_bounds__(64) void cols_kernel(const AlignArgs a) {
             const GroupRec r = grec[g];
             if (r.cmd == CMD_FRESH) {
                 const uint64_t beyond = r.m_w >= 64 ? 0ull : (~0ull << r.m_w);
-                const uint32_t tql = (uint32_t)(r.tlo >> (CB * q)), tqh = (uint32_t)(r.thi >> (CB * q));
+                const uint32_t tql = CB * q < 64 ? (uint32_t)(r.tlo >> (CB * q)) : 0u;
+                const uint32_t tqh = CB * q < 64 ? (uint32_t)(r.thi >> (CB * q)) : 0u;
                 const int ncols = min(max(r.n_w - CB * q, 0), CB);   // this lane's columns inside the text window
 #pragma unroll
                 for (int t = 0; t < CB; ++t) {
@@ -330,8 +334,10 @@ __global__ __launch_bounds__(64) void cols_kernel(const AlignArgs a) {
                         uint32_t hw[CB / 2];
 #pragma unroll
                         for (int t = 0; t < CB; t += 2) hw[t >> 1] = __builtin_amdgcn_perm(A.hi[t + 1], A.hi[t], 0x05040100u);
-                        if constexpr (CB == 4) {
-                            *reinterpret_cast<uint2*>(hp) = uint2{hw[0], hw[1]};
+                        if constexpr (CB % 8 != 0) {
+                            // 8-byte stores: a lane's high words start on an 8-byte boundary
+#pragma unroll
+                            for (int t = 0; t < CB / 2; t += 2) reinterpret_cast<uint2*>(hp)[t >> 1] = uint2{hw[t], hw[t + 1]};
                         } else {
 #pragma unroll
                             for (int t = 0; t < CB / 2; t += 4)
@@ -536,7 +542,8 @@ __global__ __launch_bounds__(64) void cols_kernel(const AlignArgs a) {
 
 int cols_dent_stride(int cap, int ng) {
     const int cols = cap + 1 < 64 ? cap + 1 : 64;   // stored columns 0..min(cap, 63)
-    return (cols + ng - 1) / ng * ng;               // whole lanes of CB = ng columns
+    const int cb = cols_per_lane(ng);
+    return (cols + cb - 1) / cb * cb;               // whole lanes of CB columns
 }
 
 size_t cols_dent_bytes(int grid, int cap, int ng) {
@@ -557,11 +564,15 @@ static const void* cols_fn(int ng) {
     }
 }
 
-// plain mode also has 32 windows per wavefront: two lanes per window, 32
-// columns each (the lane-per-pair end of the mapping)
+// plain mode also has 32 windows per wavefront (two lanes per window, 32
+// columns each: the lane-per-pair end of the mapping) and 10 (six lanes of 12
+// columns; four lanes idle), which puts one wavefront on each SIMD for about
+// ten pairs per SIMD
 template <int ST>
 static const void* cols_fn_plain(int ng) {
-    return ng == 32 ? (const void*)cols_kernel<false, 32, ST> : cols_fn<false, ST>(ng);
+    if (ng == 32) return (const void*)cols_kernel<false, 32, ST>;
+    if (ng == 10) return (const void*)cols_kernel<false, 10, ST>;
+    return cols_fn<false, ST>(ng);
 }
 
 int cols_max_blocks_per_cu(bool learned, int ng, size_t lds, int cap) {
@@ -582,6 +593,7 @@ hipError_t launch_align_cols(const AlignArgs& a, int grid, int ng, size_t lds, h
         if (ng == 4) SCG_COLS_LAUNCH(false, 4, STV);        \
         else if (ng == 8) SCG_COLS_LAUNCH(false, 8, STV);   \
         else if (ng == 16) SCG_COLS_LAUNCH(false, 16, STV); \
+        else if (ng == 10) SCG_COLS_LAUNCH(false, 10, STV); \
         else SCG_COLS_LAUNCH(false, 32, STV);               \
     } while (0)
     if (learned) {

@@ -43,6 +43,9 @@ struct scg_batch {
     Plane2* tplanes = nullptr;
     int64_t pwords = 0, twords = 0;
     int64_t pbytes = 0, tbytes = 0;   // input bytes (the packer reads no further)
+    int32_t input_kind = SCG_INPUT_ASCII;
+    int64_t* pin_d = nullptr;         // packed input: first uint64 of each sequence (npairs + 1)
+    int64_t* tin_d = nullptr;
     int64_t* pword_d = nullptr;
     int64_t* tword_d = nullptr;
     int32_t* plen_d = nullptr;
@@ -140,10 +143,27 @@ void free_batch(scg_batch* b) {
             if (e) (void)hipEventDestroy(e);
     void* ptrs[] = {b->own_seq ? b->pat_d : nullptr, b->own_seq ? b->txt_d : nullptr, b->pat_off_d, b->txt_off_d,
                     b->pplanes, b->tplanes, b->pword_d, b->tword_d, b->plen_d, b->tlen_d, b->bad_d, b->order_d,
-                    b->runs_off_d, b->qctl_d, b->ring_d, b->pstate_d, b->stats_d, b->dent_d};
+                    b->runs_off_d, b->qctl_d, b->ring_d, b->pstate_d, b->stats_d, b->dent_d, b->pin_d, b->tin_d};
     for (void* q : ptrs)
         if (q) (void)hipFree(q);
     delete b;
+}
+
+// ASCII bytes or pre-packed 2-bit words -> the planar layout of the kernels
+int enqueue_pack(scg_batch* b, hipStream_t s) {
+    const scg_ctx* c = b->ctx;
+    if (b->input_kind == SCG_INPUT_PACKED2) {
+        HIP_TRY(launch_repack2((const uint64_t*)b->pat_d, b->pin_d, b->plen_d, b->pword_d, b->npairs, b->pwords,
+                               b->pplanes, c->num_cu, s));
+        HIP_TRY(launch_repack2((const uint64_t*)b->txt_d, b->tin_d, b->tlen_d, b->tword_d, b->npairs, b->twords,
+                               b->tplanes, c->num_cu, s));
+        return SCG_OK;
+    }
+    HIP_TRY(launch_pack(b->pat_d, b->pat_off_d, b->pword_d, b->npairs, b->pwords, b->pbytes, b->pplanes, b->bad_d,
+                        c->num_cu, s));
+    HIP_TRY(launch_pack(b->txt_d, b->txt_off_d, b->tword_d, b->npairs, b->twords, b->tbytes, b->tplanes, b->bad_d,
+                        c->num_cu, s));
+    return SCG_OK;
 }
 
 int enqueue_run(scg_batch* b, hipStream_t s, int32_t* edits, int32_t* text_end, int32_t* status, uint32_t* runs,
@@ -156,10 +176,8 @@ int enqueue_run(scg_batch* b, hipStream_t s, int32_t* edits, int32_t* text_end, 
         HIP_TRY(hipEventRecord(ev[0], s));
     }
     HIP_TRY(launch_reset(b->qctl_d, b->ring_d, b->qcap, b->order_d, b->stats_d, b->bad_d, b->npairs, s));
-    HIP_TRY(launch_pack(b->pat_d, b->pat_off_d, b->pword_d, b->npairs, b->pwords, b->pbytes, b->pplanes, b->bad_d,
-                        c->num_cu, s));
-    HIP_TRY(launch_pack(b->txt_d, b->txt_off_d, b->tword_d, b->npairs, b->twords, b->tbytes, b->tplanes, b->bad_d,
-                        c->num_cu, s));
+    int prc = enqueue_pack(b, s);
+    if (prc) return prc;
     if (with_events) HIP_TRY(hipEventRecord(ev[1], s));
     AlignArgs a{};
     a.pplanes = b->pplanes;
@@ -221,6 +239,43 @@ int enqueue_run(scg_batch* b, hipStream_t s, int32_t* edits, int32_t* text_end, 
 
 }  // namespace
 
+// Predictor file (little-endian): "SCGW", uint32 version 1, int32 F, H, C,
+// int32 budget_rows[C], then FP16 w1[F*H], b1[H], w2[H*C], b2[C], row-major,
+// and nothing after.
+static int load_weights_file(scg_ctx* c, const char* path) {
+    FILE* f = std::fopen(path, "rb");
+    if (!f) {
+        std::snprintf(g_last_error, sizeof g_last_error, "cannot open predictor file %s", path);
+        return SCG_EINVAL;
+    }
+    std::vector<unsigned char> buf;
+    unsigned char tmp[4096];
+    size_t got;
+    while ((got = std::fread(tmp, 1, sizeof tmp, f)) > 0) buf.insert(buf.end(), tmp, tmp + got);
+    std::fclose(f);
+    auto bad = [&](const char* why) {
+        std::snprintf(g_last_error, sizeof g_last_error, "predictor file %s: %s", path, why);
+        return SCG_EINVAL;
+    };
+    if (buf.size() < 20 || std::memcmp(buf.data(), "SCGW", 4) != 0) return bad("not a predictor file");
+    int32_t hdr[4];
+    std::memcpy(hdr, buf.data() + 4, sizeof hdr);
+    const int32_t version = hdr[0], F = hdr[1], H = hdr[2], C = hdr[3];
+    if (version != 1) return bad("unknown version");
+    if (F != kFeatures || H < 1 || H > kMaxHidden || C < 1 || C > 4) return bad("unsupported shape");
+    const size_t nh = (size_t)F * H + H + (size_t)H * C + C;
+    if (buf.size() != 20 + 4 * (size_t)C + 2 * nh) return bad("wrong size");
+    std::vector<int32_t> rows(C);
+    std::memcpy(rows.data(), buf.data() + 20, 4 * (size_t)C);
+    std::vector<uint16_t> w(nh);
+    std::memcpy(w.data(), buf.data() + 20 + 4 * (size_t)C, 2 * nh);
+    const uint16_t* w1 = w.data();
+    const uint16_t* b1 = w1 + (size_t)F * H;
+    const uint16_t* w2 = b1 + H;
+    const uint16_t* b2 = w2 + (size_t)H * C;
+    return scg_set_model(c, F, H, C, w1, b1, w2, b2, rows.data());
+}
+
 // helpers for the allocation-free entry point (noalloc.hip)
 int capi_check_params(const scg_params* p) { return check_params(p); }
 int capi_from_hip(hipError_t e, const char* what) { return from_hip(e, what); }
@@ -258,7 +313,7 @@ void scg_params_default(scg_params* p) {
     p->yield_chars = -1;
 }
 
-int scg_create(scg_ctx** out, int device) {
+int scg_create(scg_ctx** out, int device, const char* weights_path) {
     if (!out) return SCG_EINVAL;
     *out = nullptr;
     int n = 0;
@@ -274,6 +329,13 @@ int scg_create(scg_ctx** out, int device) {
     // device address of the allocation-free workspace (looked up once per
     // device; a failure here is reported by scg_align_batch_noalloc itself)
     (void)noalloc_init(device);
+    if (weights_path) {
+        const int rc = load_weights_file(c, weights_path);
+        if (rc) {
+            scg_destroy(c);
+            return rc;
+        }
+    }
     *out = c;
     return SCG_OK;
 }
@@ -356,11 +418,14 @@ int scg_set_model(scg_ctx* c, int32_t F, int32_t H, int32_t C, const uint16_t* w
 }
 
 int scg_batch_create(scg_ctx* c, const scg_params* params, int32_t npairs, const void* pat, const int64_t* pat_off,
-                     const void* txt, const int64_t* txt_off, int32_t where, void* stream, scg_batch** out) {
+                     const void* txt, const int64_t* txt_off, int32_t input_kind, int32_t where, void* stream,
+                     scg_batch** out) {
     if (!out) return SCG_EINVAL;
     *out = nullptr;
     if (!c || npairs < 0 || !pat_off || !txt_off) return SCG_EINVAL;
     if (where != SCG_WHERE_HOST && where != SCG_WHERE_DEVICE) return SCG_EINVAL;
+    if (input_kind != SCG_INPUT_ASCII && input_kind != SCG_INPUT_PACKED2) return SCG_EINVAL;
+    const bool packed = input_kind == SCG_INPUT_PACKED2;
     int rc = check_params(params);
     if (rc) return rc;
     if (params->mode == SCG_MODE_LEARNED && !c->has_model) return SCG_ENOMODEL;
@@ -369,9 +434,21 @@ int scg_batch_create(scg_ctx* c, const scg_params* params, int32_t npairs, const
         const int64_t m = pat_off[i + 1] - pat_off[i], n = txt_off[i + 1] - txt_off[i];
         if (m < 0 || n < 0 || m > (1 << 30) || n > (1 << 30)) return SCG_EINVAL;
     }
-    const int64_t pbytes = pat_off[npairs], tbytes = txt_off[npairs];
+    // ASCII: offsets count bytes.  Packed: offsets count bases, and sequence i
+    // starts at uint64 word sum over j < i of ceil(len_j / 32).
+    std::vector<int64_t> pin, tin;
+    if (packed) {
+        pin.assign(npairs + 1, 0);
+        tin.assign(npairs + 1, 0);
+        for (int32_t i = 0; i < npairs; ++i) {
+            pin[i + 1] = pin[i] + (pat_off[i + 1] - pat_off[i] + 31) / 32;
+            tin[i + 1] = tin[i] + (txt_off[i + 1] - txt_off[i] + 31) / 32;
+        }
+    }
+    const int64_t pbytes = packed ? pin[npairs] * 8 : pat_off[npairs];
+    const int64_t tbytes = packed ? tin[npairs] * 8 : txt_off[npairs];
     if ((pbytes > 0 && !pat) || (tbytes > 0 && !txt)) return SCG_EINVAL;
-    if (where == SCG_WHERE_HOST) {
+    if (where == SCG_WHERE_HOST && !packed) {
         const uint8_t* ps = (const uint8_t*)pat;
         const uint8_t* ts = (const uint8_t*)txt;
         for (int64_t i = 0; i < pbytes; ++i)
@@ -386,6 +463,7 @@ int scg_batch_create(scg_ctx* c, const scg_params* params, int32_t npairs, const
     b->ctx = c;
     b->p = *params;
     b->npairs = npairs;
+    b->input_kind = input_kind;
     // automatic: column blocks for plain mode, error-row lanes when windows
     // start with a row budget (there lanes above the budget are saved)
     b->cols = params->kernel == SCG_KERNEL_COLUMNS ||
@@ -438,6 +516,7 @@ int scg_batch_create(scg_ctx* c, const scg_params* params, int32_t npairs, const
         (rc = dev_alloc(&b->ring_d, (size_t)b->qcap)) || (rc = dev_alloc(&b->pstate_d, (size_t)npairs * 8)) ||
         (rc = dev_alloc(&b->stats_d, ST_COUNT)))
         return fail(rc);
+    if (packed && ((rc = dev_alloc(&b->pin_d, npairs + 1)) || (rc = dev_alloc(&b->tin_d, npairs + 1)))) return fail(rc);
     if (where == SCG_WHERE_HOST) {
         b->own_seq = true;
         if ((rc = dev_alloc(&b->pat_d, (size_t)pbytes)) || (rc = dev_alloc(&b->txt_d, (size_t)tbytes))) return fail(rc);
@@ -458,7 +537,9 @@ int scg_batch_create(scg_ctx* c, const scg_params* params, int32_t npairs, const
                {b->plen_d, pl.data(), sizeof(int32_t) * npairs},
                {b->tlen_d, tl.data(), sizeof(int32_t) * npairs},
                {b->order_d, order.data(), sizeof(int32_t) * npairs},
-               {b->runs_off_d, b->runs_off_h.data(), sizeof(int64_t) * (npairs + 1)}};
+               {b->runs_off_d, b->runs_off_h.data(), sizeof(int64_t) * (npairs + 1)},
+               {b->pin_d, packed ? pin.data() : nullptr, packed ? sizeof(int64_t) * (npairs + 1) : 0},
+               {b->tin_d, packed ? tin.data() : nullptr, packed ? sizeof(int64_t) * (npairs + 1) : 0}};
     for (auto& u : ups)
         if (u.bytes && (rc = from_hip(hipMemcpyAsync(u.dst, u.src, u.bytes, hipMemcpyHostToDevice, s)))) return fail(rc);
     // host vectors die at return: wait for the copies
@@ -479,7 +560,10 @@ int scg_batch_create(scg_ctx* c, const scg_params* params, int32_t npairs, const
         // windows per wavefront: 4, 8 or 16; automatic = enough wavefronts to
         // give every SIMD two of them
         if (params->slots > 0)
-            b->ns = params->slots <= 4 ? 4 : (params->slots <= 8 ? 8 : (params->slots <= 16 ? 16 : 32));
+            b->ns = params->slots <= 4 ? 4
+                  : params->slots <= 8 ? 8
+                  : (params->slots <= 10 && !learned) ? 10
+                  : params->slots <= 16 ? 16 : 32;
         else b->ns = npairs >= 8 * c->num_cu ? 8 : 4;
         b->lds = 0;
         per_cu = cols_max_blocks_per_cu(learned, b->ns, b->lds, params->W - params->O);
@@ -632,7 +716,7 @@ int scg_align(scg_ctx* c, const char* pattern, int32_t m, const char* text, int3
     p.k = k;
     const int64_t po[2] = {0, m}, to[2] = {0, n};
     scg_batch* b = nullptr;
-    int rc = scg_batch_create(c, &p, 1, pattern, po, text, to, SCG_WHERE_HOST, nullptr, &b);
+    int rc = scg_batch_create(c, &p, 1, pattern, po, text, to, SCG_INPUT_ASCII, SCG_WHERE_HOST, nullptr, &b);
     if (rc) return rc;
     const int64_t cap = scg_batch_runs_capacity(b);
     int32_t* outs = nullptr;
@@ -661,47 +745,104 @@ int scg_align(scg_ctx* c, const char* pattern, int32_t m, const char* text, int3
 }
 
 int scg_align_batch(scg_ctx* c, const scg_params* params, int32_t npairs, const void* pat, const int64_t* pat_off,
-                    const void* txt, const int64_t* txt_off, int32_t where, void* stream, int32_t* edits,
-                    int32_t* text_end, int32_t* status, uint32_t* runs, int32_t* n_runs) {
-    if (!c || npairs < 0 || (npairs > 0 && (!edits || !text_end || !status || !runs || !n_runs))) return SCG_EINVAL;
+                    const void* txt, const int64_t* txt_off, int32_t input_kind, int32_t where, void* stream,
+                    int32_t* edits, int32_t* text_end, int32_t* status, uint8_t* ops, const int64_t* ops_off,
+                    int32_t* n_ops) {
+    if (!c || npairs < 0 || !pat_off || !txt_off) return SCG_EINVAL;
+    if (npairs > 0 && (!edits || !text_end || !status || !ops || !ops_off || !n_ops)) return SCG_EINVAL;
+    // every pair's op stream needs ceil((m + n) / 4) bytes (an operation consumes a
+    // pattern or a text character)
+    for (int32_t i = 0; i < npairs; ++i) {
+        const int64_t need = (pat_off[i + 1] - pat_off[i] + txt_off[i + 1] - txt_off[i] + 3) / 4;
+        if (ops_off[i] < 0 || ops_off[i + 1] - ops_off[i] < need) return SCG_ERANGE;
+    }
     scg_batch* b = nullptr;
-    int rc = scg_batch_create(c, params, npairs, pat, pat_off, txt, txt_off, where, stream, &b);
+    int rc = scg_batch_create(c, params, npairs, pat, pat_off, txt, txt_off, input_kind, where, stream, &b);
     if (rc) return rc;
     hipStream_t s = (hipStream_t)stream;
-    if (where == SCG_WHERE_DEVICE) {
-        rc = scg_batch_run(b, stream, edits, text_end, status, runs, n_runs);
-    } else {
-        // host outputs: run into device buffers, then copy back
-        const int64_t cap = scg_batch_runs_capacity(b);
-        int32_t* outs = nullptr;
-        uint32_t* runs_d = nullptr;
-        rc = dev_alloc(&outs, 4 * (size_t)npairs);
+    const int64_t cap = scg_batch_runs_capacity(b);
+    const bool host = where == SCG_WHERE_HOST;
+    const int64_t obytes = npairs > 0 ? ops_off[npairs] : 0;
+    uint32_t* runs_d = nullptr;
+    int32_t* rend_d = nullptr;
+    int32_t* nr_d = nullptr;
+    int64_t* ooff_d = nullptr;
+    int32_t* outs = nullptr;     // host outputs: edits, text_end, status, n_ops on the device
+    uint8_t* ops_d = nullptr;
+    if (npairs > 0) {
         if (!rc) rc = dev_alloc(&runs_d, (size_t)cap);
-        if (!rc) rc = scg_batch_run(b, stream, outs, outs + npairs, outs + 2 * (size_t)npairs, runs_d,
-                                    outs + 3 * (size_t)npairs);
+        if (!rc) rc = dev_alloc(&rend_d, (size_t)cap);
+        if (!rc) rc = dev_alloc(&nr_d, (size_t)npairs);
+        if (!rc) rc = dev_alloc(&ooff_d, (size_t)npairs + 1);
+        if (!rc && host) rc = dev_alloc(&outs, 4 * (size_t)npairs);
+        if (!rc && host) rc = dev_alloc(&ops_d, (size_t)std::max<int64_t>(obytes, 1));
+        if (!rc) rc = from_hip(hipMemcpyAsync(ooff_d, ops_off, sizeof(int64_t) * (npairs + 1), hipMemcpyHostToDevice, s));
+        int32_t* e = host ? outs : edits;
+        int32_t* te = host ? outs + npairs : text_end;
+        int32_t* st = host ? outs + 2 * (size_t)npairs : status;
+        int32_t* no = host ? outs + 3 * (size_t)npairs : n_ops;
+        uint8_t* od = host ? ops_d : ops;
+        if (!rc) rc = scg_batch_run(b, stream, e, te, st, runs_d, nr_d);
+        if (!rc) rc = from_hip(launch_runs_to_ops(runs_d, b->runs_off_d, nr_d, npairs, rend_d, od, ooff_d, no,
+                                                  c->num_cu, s), "runs to ops");
         const size_t n4 = sizeof(int32_t) * (size_t)npairs;
-        if (!rc && npairs > 0) {
-            rc = from_hip(hipMemcpyAsync(edits, outs, n4, hipMemcpyDeviceToHost, s));
-            if (!rc) rc = from_hip(hipMemcpyAsync(text_end, outs + npairs, n4, hipMemcpyDeviceToHost, s));
-            if (!rc) rc = from_hip(hipMemcpyAsync(status, outs + 2 * (size_t)npairs, n4, hipMemcpyDeviceToHost, s));
-            if (!rc) rc = from_hip(hipMemcpyAsync(n_runs, outs + 3 * (size_t)npairs, n4, hipMemcpyDeviceToHost, s));
-            if (!rc) rc = from_hip(hipMemcpyAsync(runs, runs_d, sizeof(uint32_t) * (size_t)cap, hipMemcpyDeviceToHost, s));
+        if (!rc && host) {
+            rc = from_hip(hipMemcpyAsync(edits, e, n4, hipMemcpyDeviceToHost, s));
+            if (!rc) rc = from_hip(hipMemcpyAsync(text_end, te, n4, hipMemcpyDeviceToHost, s));
+            if (!rc) rc = from_hip(hipMemcpyAsync(status, st, n4, hipMemcpyDeviceToHost, s));
+            if (!rc) rc = from_hip(hipMemcpyAsync(n_ops, no, n4, hipMemcpyDeviceToHost, s));
+            if (!rc && obytes > 0) rc = from_hip(hipMemcpyAsync(ops, ops_d, (size_t)obytes, hipMemcpyDeviceToHost, s));
         }
-        if (!rc) rc = from_hip(hipStreamSynchronize(s));
-        if (outs) (void)hipFree(outs);
-        if (runs_d) (void)hipFree(runs_d);
+        // the caller's host offsets and this call's buffers are in use until here
+        const int src = from_hip(hipStreamSynchronize(s));
+        if (!rc) rc = src;
     }
-    scg_stats st{};
-    const int src = rc ? rc : scg_batch_stats(b, &st);   // also waits for a device-output run
+    scg_stats stt{};
+    const int brc = rc ? rc : scg_batch_stats(b, &stt);
+    for (void* q : {(void*)runs_d, (void*)rend_d, (void*)nr_d, (void*)ooff_d, (void*)outs, (void*)ops_d})
+        if (q) (void)hipFree(q);
     scg_batch_destroy(b);
-    if (src && src != SCG_EINTERNAL) return src;
-    c->last = st;
-    return src;
+    if (brc && brc != SCG_EINTERNAL) return brc;
+    c->last = stt;
+    return brc;
 }
 
-int scg_last_stats(const scg_ctx* c, scg_stats* out) {
+int scg_last_stats(const scg_ctx* c, double* kernel_ms, int64_t* ops_alg, int64_t* fallback_windows) {
+    if (!c) return SCG_EINVAL;
+    if (kernel_ms) *kernel_ms = c->last.kernel_ms;
+    if (ops_alg) *ops_alg = c->last.ops_alg;
+    if (fallback_windows) *fallback_windows = c->last.fallback_windows;
+    return SCG_OK;
+}
+
+int scg_last_stats_all(const scg_ctx* c, scg_stats* out) {
     if (!c || !out) return SCG_EINVAL;
     *out = c->last;
+    return SCG_OK;
+}
+
+int scg_ops_to_cigar(const uint8_t* ops, int32_t n_ops, char* cigar, int32_t cap, int32_t* len) {
+    if ((!ops && n_ops > 0) || n_ops < 0 || !len || (!cigar && cap > 0)) return SCG_EINVAL;
+    static const char sym[4] = {'=', 'X', 'I', 'D'};
+    auto op_at = [&](int32_t t) { return (ops[t >> 2] >> (2 * (t & 3))) & 3; };
+    char tmp[16];
+    int64_t need = 0;
+    for (int32_t t = 0; t < n_ops;) {
+        int32_t e = t;
+        while (e < n_ops && op_at(e) == op_at(t)) ++e;
+        need += std::snprintf(tmp, sizeof tmp, "%d%c", e - t, sym[op_at(t)]);
+        t = e;
+    }
+    *len = (int32_t)need;
+    if (need + 1 > cap) return SCG_ERANGE;
+    int64_t at = 0;
+    for (int32_t t = 0; t < n_ops;) {
+        int32_t e = t;
+        while (e < n_ops && op_at(e) == op_at(t)) ++e;
+        at += std::snprintf(cigar + at, (size_t)(cap - at), "%d%c", e - t, sym[op_at(t)]);
+        t = e;
+    }
+    cigar[at] = '\0';
     return SCG_OK;
 }
 
@@ -711,10 +852,8 @@ int scg_features(scg_batch* b, int32_t nwin, const int32_t* windows, uint16_t* f
     hipStream_t s = (hipStream_t)stream;
     // planes are produced by the pack step of a run; make sure they exist
     HIP_TRY(launch_reset(b->qctl_d, b->ring_d, b->qcap, b->order_d, b->stats_d, b->bad_d, b->npairs, s));
-    HIP_TRY(launch_pack(b->pat_d, b->pat_off_d, b->pword_d, b->npairs, b->pwords, b->pbytes, b->pplanes, b->bad_d,
-                        b->ctx->num_cu, s));
-    HIP_TRY(launch_pack(b->txt_d, b->txt_off_d, b->tword_d, b->npairs, b->twords, b->tbytes, b->tplanes, b->bad_d,
-                        b->ctx->num_cu, s));
+    int prc = enqueue_pack(b, s);
+    if (prc) return prc;
     HIP_TRY(launch_features(b->pplanes, b->tplanes, b->pword_d, b->tword_d, b->plen_d, b->tlen_d, b->npairs, b->p.W,
                             nwin, windows, features, s));
     return SCG_OK;
@@ -732,14 +871,20 @@ int scg_mlp_forward(int32_t B, int32_t F, int32_t H, int32_t C, const uint16_t* 
     return SCG_OK;
 }
 
+int64_t scg_mlp_backward_workspace(int32_t B, int32_t H, int32_t C) {
+    if (B < 0 || H < 1 || H > kMaxHidden || C < 1 || C > 4) return -1;
+    return mlp_backward_workspace_floats(B, H, C);
+}
+
 int scg_mlp_backward(int32_t B, int32_t F, int32_t H, int32_t C, const uint16_t* x, const uint16_t* hidden,
                      const uint16_t* w2, const float* dlogits, float* gw1, float* gb1, float* gw2, float* gb2,
-                     void* stream) {
+                     float* workspace, int64_t workspace_floats, void* stream) {
     if (B < 0 || F != kFeatures || H < 1 || H > kMaxHidden || C < 1 || C > 4) return SCG_EINVAL;
     if (!gw1 || !gb1 || !gw2 || !gb2) return SCG_EINVAL;
-    if (B > 0 && (!x || !hidden || !w2 || !dlogits)) return SCG_EINVAL;
+    if (B > 0 && (!x || !hidden || !w2 || !dlogits || !workspace)) return SCG_EINVAL;
+    if (workspace_floats < mlp_backward_workspace_floats(B, H, C)) return SCG_ERANGE;
     HIP_TRY(launch_mlp_backward(B, F, H, C, (const __half*)x, (const __half*)hidden, (const __half*)w2, dlogits,
-                                gw1, gb1, gw2, gb2, (hipStream_t)stream));
+                                gw1, gb1, gw2, gb2, workspace, (hipStream_t)stream));
     return SCG_OK;
 }
 

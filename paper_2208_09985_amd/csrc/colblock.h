@@ -7,6 +7,13 @@ namespace colblock {
 
 constexpr uint32_t kDppWaveShl1 = 0x130;
 
+// Text columns per lane for NG windows of 64 / NG lanes each: enough to cover
+// 64 columns, rounded up to whole groups of four (the row update's unit).
+__host__ __device__ constexpr int cols_per_lane(int ng) {
+    const int l = 64 / ng;
+    return ((64 + l - 1) / l + 3) / 4 * 4;
+}
+
 __device__ __forceinline__ uint32_t from_upper_lane(uint32_t x) {
     // lane l receives lane l+1's value; lane 63 receives 0
     return (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, kDppWaveShl1, 0xF, 0xF, true);

@@ -103,7 +103,13 @@ hipError_t launch_mlp_forward(int32_t B, int32_t F, int32_t H, int32_t C, const 
                               hipStream_t s);
 hipError_t launch_mlp_backward(int32_t B, int32_t F, int32_t H, int32_t C, const __half* x,
                                const __half* hidden, const __half* w2, const float* dlogits, float* gw1,
-                               float* gb1, float* gw2, float* gb2, hipStream_t s);
+                               float* gb1, float* gw2, float* gb2, float* workspace, hipStream_t s);
+int64_t mlp_backward_workspace_floats(int32_t B, int32_t H, int32_t C);
+hipError_t launch_repack2(const uint64_t* in, const int64_t* inword, const int32_t* len, const int64_t* wordoff,
+                          int32_t nseq, int64_t total_words, Plane2* out, int num_cu, hipStream_t s);
+hipError_t launch_runs_to_ops(const uint32_t* runs, const int64_t* runs_off, const int32_t* n_runs, int32_t npairs,
+                              int32_t* rend, uint8_t* ops, const int64_t* ops_off, int32_t* n_ops, int num_cu,
+                              hipStream_t s);
 int noalloc_init(int device);   // noalloc.hip: device address of its static workspace
 hipError_t launch_adam(int32_t n, float* p, const float* g, float* m, float* v, __half* p16, float lr,
                        float b1, float b2, float eps, int32_t step, hipStream_t s);

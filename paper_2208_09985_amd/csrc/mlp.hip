@@ -145,9 +145,6 @@ __global__ __launch_bounds__(256) void adam_kernel(int32_t n, float* __restrict_
     p16[t] = __float2half(pt);
 }
 
-float* g_partial = nullptr;
-size_t g_partial_bytes = 0;
-
 }  // namespace
 
 hipError_t launch_features(const Plane2* pplanes, const Plane2* tplanes, const int64_t* pword, const int64_t* tword,
@@ -169,23 +166,22 @@ hipError_t launch_mlp_forward(int32_t B, int32_t F, int32_t H, int32_t C, const 
     return hipGetLastError();
 }
 
+// per-block partial gradients: one row of P floats per chunk of samples
+int64_t mlp_backward_workspace_floats(int32_t B, int32_t H, int32_t C) {
+    if (B <= 0) return 0;
+    const int chunk = 256;
+    const int64_t nblocks = (B + chunk - 1) / chunk;
+    return nblocks * (int64_t)(kFeatures * H + H + H * C + C);
+}
+
 hipError_t launch_mlp_backward(int32_t B, int32_t F, int32_t H, int32_t C, const __half* x, const __half* hidden,
                                const __half* w2, const float* dlogits, float* gw1, float* gb1, float* gw2, float* gb2,
-                               hipStream_t s) {
+                               float* g_partial, hipStream_t s) {
     (void)F;
     if (B <= 0) return hipSuccess;
     const int chunk = 256;
     const int nblocks = (B + chunk - 1) / chunk;
     const int P = kFeatures * H + H + H * C + C;
-    const size_t need = (size_t)nblocks * P * sizeof(float);
-    if (need > g_partial_bytes) {
-        if (g_partial) (void)hipFree(g_partial);
-        g_partial = nullptr;
-        g_partial_bytes = 0;
-        hipError_t e = hipMalloc(&g_partial, need);
-        if (e != hipSuccess) return e;
-        g_partial_bytes = need;
-    }
     hipLaunchKernelGGL(mlp_backward_partial, dim3(nblocks), dim3(64), 0, s, B, H, C, chunk, x, hidden, w2, dlogits,
                        g_partial);
     hipError_t e = hipGetLastError();

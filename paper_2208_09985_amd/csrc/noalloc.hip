@@ -193,7 +193,8 @@ extern "C" int scg_align_batch_noalloc(scg_ctx* c, const scg_params* params, int
     // grid capped by the stored-row region of the workspace
     const int num_cu = scg_device_cus(c);
     const int ns = params->slots > 0
-                       ? (params->slots <= 4 ? 4 : (params->slots <= 8 ? 8 : (params->slots <= 16 ? 16 : 32)))
+                       ? (params->slots <= 4 ? 4 : params->slots <= 8 ? 8 : params->slots <= 10 ? 10
+                          : params->slots <= 16 ? 16 : 32)
                        : (npairs >= 8 * num_cu ? 8 : 4);
     const int cap = params->W - params->O;
     int grid = cols_max_blocks_per_cu(false, ns, 0, cap) * num_cu;

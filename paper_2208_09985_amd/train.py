@@ -90,11 +90,16 @@ def forward(lib, mlp, x16, labels=None, stream=None):
 
 
 def backward(lib, mlp, x16, hidden, dlogits, stream=None):
+    import torch
     gw1, gb1, gw2, gb2 = mlp.views(mlp.g)
     _, _, w2, _ = mlp.views(mlp.p16)
     P = api._ptr
+    need = int(lib.scg_mlp_backward_workspace(x16.shape[0], mlp.H, mlp.C))
+    ws = getattr(mlp, "workspace", None)
+    if ws is None or ws.numel() < max(need, 1):
+        ws = mlp.workspace = torch.empty(max(need, 1), dtype=torch.float32, device=x16.device)
     rc = lib.scg_mlp_backward(x16.shape[0], F, mlp.H, mlp.C, P(x16), P(hidden), P(w2), P(dlogits),
-                              P(gw1), P(gb1), P(gw2), P(gb2), api._stream_ptr(stream))
+                              P(gw1), P(gb1), P(gw2), P(gb2), P(ws), ws.numel(), api._stream_ptr(stream))
     L.check(rc, "scg_mlp_backward")
 
 
@@ -157,9 +162,27 @@ def train(windows_path=DEFAULT_WINDOWS, out=DEFAULT_OUT, epochs=12, batch_size=4
     np.savez(out, w1=w1, b1=b1, w2=w2, b2=b2, budget_rows=np.asarray(BUDGET_ROWS, np.int32),
              feature_scale=np.float32(1 / 64), windows=np.int64(N), workload=workload,
              val_acc=np.float32(hist[-1]["val_acc"]), val_loss=np.float32(hist[-1]["val_loss"]))
+    write_scgw(out, os.path.splitext(out)[0] + ".scgw")
     log(f"[train] {N} windows, {time.time() - t0:.1f}s -> {out}")
     keep.close()
     return hist
+
+
+def write_scgw(npz_path: str, out: str) -> None:
+    """The predictor file scg_create reads: "SCGW", uint32 version 1, int32 F,
+    H, C, int32 budget_rows[C], then FP16 w1, b1, w2, b2 (little-endian)."""
+    z = np.load(npz_path, allow_pickle=False)
+    w1, b1, w2, b2 = (np.ascontiguousarray(z[k], dtype=np.float16) for k in ("w1", "b1", "w2", "b2"))
+    F, H = w1.shape
+    C = w2.shape[1]
+    rows = np.ascontiguousarray(z["budget_rows"], dtype="<i4")
+    with open(out + ".tmp", "wb") as f:
+        f.write(b"SCGW")
+        f.write(np.asarray([1, F, H, C], dtype="<i4").tobytes())
+        f.write(rows.tobytes())
+        for a in (w1, b1, w2, b2):
+            f.write(a.astype("<f2").tobytes())
+    os.replace(out + ".tmp", out)
 
 
 def evaluate(lib, mlp, x16, y):

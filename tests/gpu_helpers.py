@@ -55,7 +55,16 @@ def compare(batch, gpu, ref, what=""):
         f"{what}: edits differ at {np.flatnonzero(np.asarray(gpu.edits)[:n] != ref['edits'])[:10]}")
     assert np.array_equal(np.asarray(gpu.text_end)[:n], ref["text_end"]), (
         f"{what}: text_end differs at {np.flatnonzero(np.asarray(gpu.text_end)[:n] != ref['text_end'])[:10]}")
-    ops, offs, words, n_runs = expand_runs(gpu, n)
+    if hasattr(gpu, "n_ops"):   # a 2-bit operation stream (scg_align_batch)
+        counts = np.asarray(gpu.n_ops)[:n].astype(np.int64)
+        packed = np.asarray(gpu.ops, np.uint8)
+        unpacked = np.stack([(packed >> (2 * e)) & 3 for e in range(4)], axis=1).reshape(-1).astype(np.uint8)
+        ops = _gather(unpacked, 4 * np.asarray(gpu.ops_off)[:n], counts)
+        offs = np.zeros(n + 1, np.int64)
+        np.cumsum(counts, out=offs[1:])
+        words = n_runs = None
+    else:
+        ops, offs, words, n_runs = expand_runs(gpu, n)
     ref_counts = np.asarray(ref["n_ops"])[:n].astype(np.int64)
     gpu_counts = np.diff(offs)
     bad = np.flatnonzero(gpu_counts != ref_counts)
@@ -65,6 +74,8 @@ def compare(batch, gpu, ref, what=""):
         at = int(np.argmax(ops != ref_ops))
         pair = int(np.searchsorted(offs, at, side="right") - 1)
         raise AssertionError(f"{what}: op stream of pair {pair} differs (first at op {at - int(offs[pair])})")
+    if words is None:
+        return
     # runs are maximal: no empty run and no two consecutive words of a pair with the same op
     assert np.all((words >> 2) > 0), f"{what}: empty run"
     if words.size > 1:

@@ -97,6 +97,7 @@ def test_window_parameters(ctx, W, O, k):
     b = synth.from_lists(pats, txts)
     check(ctx, b, W=W, O=O, k=k, what=f"W{W}O{O}k{k}")
     check(ctx, b, W=W, O=O, k=k, mode="fixed", fixed_rows=3, what=f"W{W}O{O}k{k} fixed3")
+    check(ctx, b, W=W, O=O, k=k, what=f"W{W}O{O}k{k} 10 windows per wavefront", kernels=("columns",), slots=10)
 
 
 def test_edge_cases(ctx):
@@ -138,7 +139,8 @@ def test_launch_shape_does_not_change_results(ctx):
     for kw in (dict(slots=1, waves_per_cu=1), dict(slots=3, order="longest_first"), dict(slots=16, waves_per_cu=2),
                dict(kernel="columns", slots=4, waves_per_cu=1), dict(kernel="columns", slots=8, order="longest_first"),
                dict(kernel="columns", slots=16, waves_per_cu=2), dict(kernel="columns", slots=32),
-               dict(kernel="columns", slots=24, waves_per_cu=1)):
+               dict(kernel="columns", slots=24, waves_per_cu=1), dict(kernel="columns", slots=10),
+               dict(kernel="columns", slots=9, waves_per_cu=1)):
         log(f"[parity] launch shape {kw}")
         kw.setdefault("kernel", "rows")
         compare(b, run_gpu(ctx, b, mode="fixed", fixed_rows=12, **kw), ref, f"shape {kw}")
@@ -197,7 +199,7 @@ def test_unrelated_pairs_long_tracebacks(ctx):
     pats = [synth.ALPHABET[rng.integers(0, 4, int(rng.integers(50, 600)))].tobytes() for _ in range(300)]
     txts = [synth.ALPHABET[rng.integers(0, 4, int(rng.integers(50, 600)))].tobytes() for _ in range(300)]
     b = synth.from_lists(pats, txts)
-    for slots in (4, 8, 16):
+    for slots in (4, 8, 10, 16):
         check(ctx, b, what=f"unrelated slots={slots}", kernels=("columns",), slots=slots)
     check(ctx, b, what="unrelated rows", kernels=("rows",))
 
@@ -222,20 +224,28 @@ def test_long_one_sided_indels(ctx):
         txts.append(t.tobytes())
     b = synth.from_lists(pats, txts)
     check(ctx, b, what="long indels")
-    for slots in (4, 16):
+    for slots in (4, 10, 16):
         check(ctx, b, what=f"long indels slots={slots}", kernels=("columns",), slots=slots)
 
 
 def test_one_shot_batch_call(ctx):
-    # scg_align_batch: host arrays in and out, and device arrays in and out
+    # scg_align_batch: host arrays in and out, and device arrays in and out, ASCII
+    # or pre-packed 2-bit input; 2-bit operation streams out, rendered by
+    # scg_ops_to_cigar
     from paper_2208_09985_amd import api
     b = synth.make_batch("uneven_lognormal", 24)
+    pats = [b.pattern(i) for i in range(b.npairs)] + [b"", b"ACGT", b"acgtT", b"G" * 130]
+    txts = [b.text(i) for i in range(b.npairs)] + [b"AC", b"", b"ACGTA", b"G" * 129 + b"T"]
+    b = synth.from_lists(pats, txts)
     ref = oracle.align_batch(b, 64, 24, 64)
     for host in (True, False):
-        log(f"[parity] one-shot batch call host={host}")
-        res = api.align_batch_once(ctx, b, host=host)
-        compare(b, res, ref, f"one-shot host={host}")
-        assert res.stats.windows > 0 and res.stats.kernel_ms > 0
+        for packed in (False, True):
+            log(f"[parity] one-shot batch call host={host} packed={packed}")
+            res = api.align_batch_once(ctx, b, host=host, packed=packed)
+            compare(b, res, ref, f"one-shot host={host} packed={packed}")
+            assert res.stats.windows == ref["stats"].windows and res.stats.kernel_ms > 0
+            for i in range(b.npairs):
+                assert res.cigar(i) == oracle.cigar(oracle.ops_of(ref, i)), i
 
 
 @pytest.mark.parametrize("W,O,k,slots", [(128, 24, 128, 0), (128, 64, 128, 8), (96, 32, 96, 0), (65, 0, 65, 4),

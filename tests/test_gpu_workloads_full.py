@@ -73,6 +73,9 @@ def test_long_10kbp_all_pairs_plain_and_learned(ctx):
     st = bt.stats()
     bt.close()
     assert st.windows == ref["stats"].windows and st.ops_alg == ref["stats"].ops_alg
+    for slots in (10, 16):
+        log(f"[full] long_10kbp plain, {slots} windows per wavefront")
+        compare(b, api.align_batch(ctx, b, kernel="columns", slots=slots), ref, f"long_10kbp full slots={slots}")
     log("[full] long_10kbp learned (committed predictor), default kernel")
     compare(b, api.align_batch(ctx, b, mode="learned"), ref, "long_10kbp full learned")
 
