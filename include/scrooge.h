@@ -90,8 +90,12 @@ enum {
     /* Ablations of the paper's improvements (Section 2.4), plain mode in the column-block     */
     /* kernel only (SCG_EINVAL otherwise); results are unchanged, only the work grows:         */
     SCG_FLAG_NO_EARLY_TERMINATION = 2,  /* every window computes all k_w+1 rows (no ET)        */
-    SCG_FLAG_STORE_ALL_COLUMNS = 4      /* store every column of a row, not only 0..W-O (no    */
+    SCG_FLAG_STORE_ALL_COLUMNS = 4,     /* store every column of a row, not only 0..W-O (no    */
                                         /* DENT)                                               */
+    SCG_FLAG_ROWS_LDS = 8               /* keep the lowest stored rows of each window in LDS   */
+                                        /* (as many as fit with the wavefronts the batch       */
+                                        /* needs; 4, 8 or 16 windows per wavefront), the rest  */
+                                        /* in global memory; by default all rows are global    */
 };
 
 /* which fused kernel aligns the batch (same results, different mappings) */

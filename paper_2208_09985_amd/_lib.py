@@ -21,6 +21,7 @@ INPUT_ASCII, INPUT_PACKED2 = 0, 1
 FLAG_GRAPH = 1
 FLAG_NO_EARLY_TERMINATION = 2
 FLAG_STORE_ALL_COLUMNS = 4
+FLAG_ROWS_LDS = 8
 KERNEL_AUTO, KERNEL_ROWS, KERNEL_COLUMNS = 0, 1, 2
 NFEATURES = 16
 

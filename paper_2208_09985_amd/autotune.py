@@ -10,6 +10,7 @@ and keeps the fastest:
 * order         -- queue order of pairs (input order or longest first)
 * tau           -- learned mode: confidence needed before a smaller row budget
 * fixed_rows    -- fixed mode: constant row budget before falling back
+* rows_lds      -- plain mode: the lowest stored rows of each window in LDS
 
 Every candidate produces bit-identical output (the budget only changes how
 many rows are tried first), which the tuner checks against the first
@@ -32,7 +33,8 @@ from . import api
 DEFAULT_CACHE = os.path.join(os.path.expanduser("~"), ".cache", "scrooge_mi355x", "autotune.json")
 
 SPACE = {
-    "plain": {"kernel": ["columns"], "slots": [4, 8, 10, 16], "waves_per_cu": [0], "order": ["input", "longest_first"]},
+    "plain": {"kernel": ["columns"], "slots": [4, 8, 10, 16], "waves_per_cu": [0], "order": ["input", "longest_first"],
+              "rows_lds": [False, True]},
     "fixed": {"kernel": ["rows"], "slots": [2, 4, 6, 8], "waves_per_cu": [0], "order": ["input"],
               "fixed_rows": [7, 11, 15, 23]},
     "learned": {"kernel": ["rows"], "slots": [2, 4, 6], "waves_per_cu": [0], "order": ["input"],

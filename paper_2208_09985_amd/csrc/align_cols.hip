@@ -86,7 +86,7 @@ struct GroupRec {      // LDS: what the slot lane tells its group at set-up
 // ST: the stored entries.  0: whole 64-bit entries.  1 (NARROW): their low 32
 // bits, when traceback reads bits 0..31 at most.  2 (SPLIT): their low 48 bits
 // as a 32-bit plane and a 16-bit plane, when it reads bits 0..47 at most.
-template <bool LEARNED, int NG, int ST>
+template <bool LEARNED, int NG, int ST, bool LR>
 __global__ __launch_bounds__(64) void cols_kernel(const AlignArgs a) {
     constexpr bool NARROW = ST == 1, SPLIT = ST == 2;
     constexpr int L = 64 / NG;             // lanes per window
@@ -114,6 +114,15 @@ __global__ __launch_bounds__(64) void cols_kernel(const AlignArgs a) {
     const uint32_t lobytes = (uint32_t)stride * 4u, hibytes = (uint32_t)stride * 2u;
     const uint32_t hiplane = gbyte + (uint32_t)kStoredRows * lobytes;
     const bool storer = CB * q < stride;
+    // Rows 0..R-1 of every group's stored region live in LDS (dynamic shared
+    // memory, R chosen by the host from the occupancy the batch needs): the
+    // same layout as the global region with R rows per group.  Rows R..63 stay
+    // in the global region.
+    extern __shared__ __align__(16) char lrows[];
+    const int R = LR ? a.lds_rows : 0;
+    const uint32_t lrowb = SPLIT ? (uint32_t)stride * 6u : rowbytes;   // bytes of one stored row
+    const uint32_t lgbyte = (uint32_t)(live ? g : 0) * (uint32_t)R * lrowb;
+    const uint32_t lhiplane = lgbyte + (uint32_t)R * lobytes;
 
     if (lane <= NG) grec[lane] = GroupRec{0, 0, 0, 0, 0, 0, 0, 0, CMD_NONE, 0};
 
@@ -319,33 +328,45 @@ __global__ __launch_bounds__(64) void cols_kernel(const AlignArgs a) {
                     zrlo = zl;
                     zrhi = zh;
                 }
-                // keep the row for traceback
+                // keep the row for traceback: rows below lds_rows in LDS, the others in
+                // the global region (same layout, other base and row count)
                 if (computing && storer && (uint32_t)dh < (uint32_t)kStoredRows) {
-                    uint4* row = reinterpret_cast<uint4*>(bdent + (soff + (h ? rowbytes : 0u)));
-                    if (NARROW) {
+                    auto put = [&](char* const base, uint32_t lo_off, uint32_t hi_off) {
+                        if (NARROW) {
+                            uint4* row = reinterpret_cast<uint4*>(base + lo_off);
 #pragma unroll
-                        for (int t = 0; t < CB; t += 4) row[t >> 2] = uint4{A.lo[t], A.lo[t + 1], A.lo[t + 2], A.lo[t + 3]};
-                    } else if (SPLIT) {
-                        // low words as they are; bits 32..47 two columns to a word
-                        uint4* lo = reinterpret_cast<uint4*>(bdent + (gbyte + __umul24((uint32_t)dh, lobytes) + (uint32_t)(CB * q) * 4u));
+                            for (int t = 0; t < CB; t += 4) row[t >> 2] = uint4{A.lo[t], A.lo[t + 1], A.lo[t + 2], A.lo[t + 3]};
+                        } else if (SPLIT) {
+                            // low words as they are; bits 32..47 two columns to a word
+                            uint4* lo = reinterpret_cast<uint4*>(base + lo_off);
 #pragma unroll
-                        for (int t = 0; t < CB; t += 4) lo[t >> 2] = uint4{A.lo[t], A.lo[t + 1], A.lo[t + 2], A.lo[t + 3]};
-                        char* const hp = bdent + (hiplane + __umul24((uint32_t)dh, hibytes) + (uint32_t)(CB * q) * 2u);
-                        uint32_t hw[CB / 2];
+                            for (int t = 0; t < CB; t += 4) lo[t >> 2] = uint4{A.lo[t], A.lo[t + 1], A.lo[t + 2], A.lo[t + 3]};
+                            char* const hp = base + hi_off;
+                            uint32_t hw[CB / 2];
 #pragma unroll
-                        for (int t = 0; t < CB; t += 2) hw[t >> 1] = __builtin_amdgcn_perm(A.hi[t + 1], A.hi[t], 0x05040100u);
-                        if constexpr (CB % 8 != 0) {
-                            // 8-byte stores: a lane's high words start on an 8-byte boundary
+                            for (int t = 0; t < CB; t += 2) hw[t >> 1] = __builtin_amdgcn_perm(A.hi[t + 1], A.hi[t], 0x05040100u);
+                            if constexpr (CB % 8 != 0) {
+                                // 8-byte stores: a lane's high words start on an 8-byte boundary
 #pragma unroll
-                            for (int t = 0; t < CB / 2; t += 2) reinterpret_cast<uint2*>(hp)[t >> 1] = uint2{hw[t], hw[t + 1]};
+                                for (int t = 0; t < CB / 2; t += 2) reinterpret_cast<uint2*>(hp)[t >> 1] = uint2{hw[t], hw[t + 1]};
+                            } else {
+#pragma unroll
+                                for (int t = 0; t < CB / 2; t += 4)
+                                    reinterpret_cast<uint4*>(hp)[t >> 2] = uint4{hw[t], hw[t + 1], hw[t + 2], hw[t + 3]};
+                            }
                         } else {
+                            uint4* row = reinterpret_cast<uint4*>(base + lo_off);
 #pragma unroll
-                            for (int t = 0; t < CB / 2; t += 4)
-                                reinterpret_cast<uint4*>(hp)[t >> 2] = uint4{hw[t], hw[t + 1], hw[t + 2], hw[t + 3]};
+                            for (int t = 0; t < CB; t += 2) row[t >> 1] = uint4{A.lo[t], A.hi[t], A.lo[t + 1], A.hi[t + 1]};
                         }
+                    };
+                    const uint32_t udh = (uint32_t)dh;
+                    if (LR && udh < (uint32_t)R) {
+                        put(lrows, lgbyte + udh * (SPLIT ? lobytes : rowbytes) + (uint32_t)(CB * q) * (SPLIT ? 4u : ESZ),
+                            lhiplane + udh * hibytes + (uint32_t)(CB * q) * 2u);
                     } else {
-#pragma unroll
-                        for (int t = 0; t < CB; t += 2) row[t >> 1] = uint4{A.lo[t], A.hi[t], A.lo[t + 1], A.hi[t + 1]};
+                        put(bdent, SPLIT ? gbyte + __umul24(udh, lobytes) + (uint32_t)(CB * q) * 4u : soff + (h ? rowbytes : 0u),
+                            hiplane + __umul24(udh, hibytes) + (uint32_t)(CB * q) * 2u);
                     }
                 }
                 // early termination: column 0 of row d has the msb of R clear.  Lane 0 of
@@ -425,27 +446,75 @@ __global__ __launch_bounds__(64) void cols_kernel(const AlignArgs a) {
                     const int ti = tb_i + L, tj = tb_j + L, td = tb_d;
                     // edit step at (ti, tj, td): bits tj, tj+1 of row td-1 at columns ti and ti+1.
                     // The loads go out first; the run bookkeeping below overlaps them.
-                    const uint32_t ro = gbyte + __umul24((uint32_t)(max(td, 1) - 1), rowbytes);
-                    const char* const e0 = bdent + (ro + (uint32_t)min(ti, stride - 1) * ESZ);
-                    const char* const e1 = bdent + (ro + (uint32_t)min(ti + 1, stride - 1) * ESZ);
                     uint64_t v0, v1;
-                    if (NARROW) {
-                        v0 = *reinterpret_cast<const uint32_t*>(e0);
-                        v1 = *reinterpret_cast<const uint32_t*>(e1);
-                    } else if (SPLIT) {
-                        // columns ti and ti+1 of both planes, as one 8-byte word each (the
-                        // 16-bit word from the 4-byte boundary at or below column ti)
-                        struct __attribute__((packed, aligned(4))) W2 { uint64_t v; };
+                    if constexpr (LR) {
                         const uint32_t rr = (uint32_t)(max(td, 1) - 1);
-                        const uint32_t c0 = (uint32_t)min(ti, stride - 1);
-                        const uint64_t lw = reinterpret_cast<const W2*>(bdent + (gbyte + __umul24(rr, lobytes) + c0 * 4u))->v;
-                        const uint64_t hw = reinterpret_cast<const W2*>(bdent + (hiplane + __umul24(rr, hibytes) + (c0 & ~1u) * 2u))->v
-                                            >> ((c0 & 1u) * 16u);
-                        v0 = (uint64_t)(uint32_t)lw | (uint64_t)(hw & 0xFFFFu) << 32;
-                        v1 = (lw >> 32) | (uint64_t)((hw >> 16) & 0xFFFFu) << 32;
+                        const uint32_t c0 = (uint32_t)min(ti, stride - 1), c1 = (uint32_t)min(ti + 1, stride - 1);
+                        const bool in_lds = rr < (uint32_t)R;
+                        struct __attribute__((packed, aligned(4))) W2 { uint64_t v; };
+                        uint64_t llw = 0, lhw = 0, glw = 0, ghw = 0;
+                        // rows below R from LDS (every lane reads, at a clamped row); the
+                        // others from the global region, skipped when no lane needs one
+                        if (R > 0) {
+                            const uint32_t rl = min(rr, (uint32_t)R - 1u);
+                            const uint32_t lo_row = lgbyte + rl * (SPLIT ? lobytes : rowbytes);
+                            if (NARROW) {
+                                llw = *reinterpret_cast<const uint32_t*>(lrows + (lo_row + c0 * ESZ));
+                                lhw = *reinterpret_cast<const uint32_t*>(lrows + (lo_row + c1 * ESZ));
+                            } else if (SPLIT) {
+                                llw = reinterpret_cast<const W2*>(lrows + (lo_row + c0 * 4u))->v;
+                                lhw = reinterpret_cast<const W2*>(lrows + (lhiplane + rl * hibytes + (c0 & ~1u) * 2u))->v;
+                            } else {
+                                llw = *reinterpret_cast<const uint64_t*>(lrows + (lo_row + c0 * ESZ));
+                                lhw = *reinterpret_cast<const uint64_t*>(lrows + (lo_row + c1 * ESZ));
+                            }
+                        }
+                        if (__ballot(!in_lds) != 0) {
+                            const uint32_t lo_row = gbyte + __umul24(rr, SPLIT ? lobytes : rowbytes);
+                            if (NARROW) {
+                                glw = *reinterpret_cast<const uint32_t*>(bdent + (lo_row + c0 * ESZ));
+                                ghw = *reinterpret_cast<const uint32_t*>(bdent + (lo_row + c1 * ESZ));
+                            } else if (SPLIT) {
+                                glw = reinterpret_cast<const W2*>(bdent + (lo_row + c0 * 4u))->v;
+                                ghw = reinterpret_cast<const W2*>(bdent + (hiplane + __umul24(rr, hibytes) + (c0 & ~1u) * 2u))->v;
+                            } else {
+                                glw = *reinterpret_cast<const uint64_t*>(bdent + (lo_row + c0 * ESZ));
+                                ghw = *reinterpret_cast<const uint64_t*>(bdent + (lo_row + c1 * ESZ));
+                            }
+                        }
+                        const uint64_t lw = in_lds ? llw : glw, hw = in_lds ? lhw : ghw;
+                        if (SPLIT) {
+                            // columns ti and ti+1 of both planes, as one 8-byte word each (the
+                            // 16-bit word from the 4-byte boundary at or below column ti)
+                            const uint64_t hs = hw >> ((c0 & 1u) * 16u);
+                            v0 = (uint64_t)(uint32_t)lw | (uint64_t)(hs & 0xFFFFu) << 32;
+                            v1 = (lw >> 32) | (uint64_t)((hs >> 16) & 0xFFFFu) << 32;
+                        } else {
+                            v0 = lw;
+                            v1 = hw;
+                        }
                     } else {
-                        v0 = *reinterpret_cast<const uint64_t*>(e0);
-                        v1 = *reinterpret_cast<const uint64_t*>(e1);
+                        const uint32_t ro = gbyte + __umul24((uint32_t)(max(td, 1) - 1), rowbytes);
+                        const char* const e0 = bdent + (ro + (uint32_t)min(ti, stride - 1) * ESZ);
+                        const char* const e1 = bdent + (ro + (uint32_t)min(ti + 1, stride - 1) * ESZ);
+                        if (NARROW) {
+                            v0 = *reinterpret_cast<const uint32_t*>(e0);
+                            v1 = *reinterpret_cast<const uint32_t*>(e1);
+                        } else if (SPLIT) {
+                            // columns ti and ti+1 of both planes, as one 8-byte word each (the
+                            // 16-bit word from the 4-byte boundary at or below column ti)
+                            struct __attribute__((packed, aligned(4))) W2 { uint64_t v; };
+                            const uint32_t rr = (uint32_t)(max(td, 1) - 1);
+                            const uint32_t c0 = (uint32_t)min(ti, stride - 1);
+                            const uint64_t lw = reinterpret_cast<const W2*>(bdent + (gbyte + __umul24(rr, lobytes) + c0 * 4u))->v;
+                            const uint64_t hw = reinterpret_cast<const W2*>(bdent + (hiplane + __umul24(rr, hibytes) + (c0 & ~1u) * 2u))->v
+                                                >> ((c0 & 1u) * 16u);
+                            v0 = (uint64_t)(uint32_t)lw | (uint64_t)(hw & 0xFFFFu) << 32;
+                            v1 = (lw >> 32) | (uint64_t)((hw >> 16) & 0xFFFFu) << 32;
+                        } else {
+                            v0 = *reinterpret_cast<const uint64_t*>(e0);
+                            v1 = *reinterpret_cast<const uint64_t*>(e1);
+                        }
                     }
                     // the run list always holds the open run at index nruns, so
                     // extending or starting a run is one unconditional store
@@ -555,31 +624,44 @@ size_t cols_dent_bytes(int grid, int cap, int ng) {
 // entries at every W-O
 static int cols_store(bool learned, int cap) { return learned ? 0 : (cap <= 31 ? 1 : (cap <= 47 ? 2 : 0)); }
 
+// bytes of one stored row of one group (both planes of the 48-bit form)
+size_t cols_lds_row_bytes(bool learned, int cap, int stride) {
+    const int st = cols_store(learned, cap);
+    return (size_t)stride * (st == 1 ? 4 : (st == 2 ? 6 : 8));
+}
+
 template <bool LEARNED, int ST>
 static const void* cols_fn(int ng) {
     switch (ng) {
-    case 4: return (const void*)cols_kernel<LEARNED, 4, ST>;
-    case 8: return (const void*)cols_kernel<LEARNED, 8, ST>;
-    default: return (const void*)cols_kernel<LEARNED, 16, ST>;
+    case 4: return (const void*)cols_kernel<LEARNED, 4, ST, false>;
+    case 8: return (const void*)cols_kernel<LEARNED, 8, ST, false>;
+    default: return (const void*)cols_kernel<LEARNED, 16, ST, false>;
     }
 }
 
 // plain mode also has 32 windows per wavefront (two lanes per window, 32
 // columns each: the lane-per-pair end of the mapping) and 10 (six lanes of 12
 // columns; four lanes idle), which puts one wavefront on each SIMD for about
-// ten pairs per SIMD
+// ten pairs per SIMD; and, with 4, 8 or 16 windows, the form that keeps the
+// lowest stored rows in LDS
 template <int ST>
-static const void* cols_fn_plain(int ng) {
-    if (ng == 32) return (const void*)cols_kernel<false, 32, ST>;
-    if (ng == 10) return (const void*)cols_kernel<false, 10, ST>;
+static const void* cols_fn_plain(int ng, bool lds_rows) {
+    if (lds_rows) {
+        if (ng == 4) return (const void*)cols_kernel<false, 4, ST, true>;
+        if (ng == 8) return (const void*)cols_kernel<false, 8, ST, true>;
+        return (const void*)cols_kernel<false, 16, ST, true>;
+    }
+    if (ng == 32) return (const void*)cols_kernel<false, 32, ST, false>;
+    if (ng == 10) return (const void*)cols_kernel<false, 10, ST, false>;
     return cols_fn<false, ST>(ng);
 }
 
-int cols_max_blocks_per_cu(bool learned, int ng, size_t lds, int cap) {
+int cols_max_blocks_per_cu(bool learned, int ng, size_t lds, int cap, bool lds_rows) {
     int nb = 0;
     const int st = cols_store(learned, cap);
     const void* f = learned ? cols_fn<true, 0>(ng)
-                  : (st == 1 ? cols_fn_plain<1>(ng) : (st == 2 ? cols_fn_plain<2>(ng) : cols_fn_plain<0>(ng)));
+                  : (st == 1 ? cols_fn_plain<1>(ng, lds_rows)
+                             : (st == 2 ? cols_fn_plain<2>(ng, lds_rows) : cols_fn_plain<0>(ng, lds_rows)));
     if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, f, 64, lds) != hipSuccess) return 1;
     return nb < 1 ? 1 : nb;
 }
@@ -587,19 +669,25 @@ int cols_max_blocks_per_cu(bool learned, int ng, size_t lds, int cap) {
 hipError_t launch_align_cols(const AlignArgs& a, int grid, int ng, size_t lds, hipStream_t s) {
     const bool learned = a.mode == 1;
     const int st = cols_store(learned, a.cap);
-#define SCG_COLS_LAUNCH(LRN, NGV, STV) hipLaunchKernelGGL((cols_kernel<LRN, NGV, STV>), dim3(grid), dim3(64), lds, s, a)
-#define SCG_COLS_PLAIN(STV)                          \
-    do {                                             \
-        if (ng == 4) SCG_COLS_LAUNCH(false, 4, STV);        \
-        else if (ng == 8) SCG_COLS_LAUNCH(false, 8, STV);   \
-        else if (ng == 16) SCG_COLS_LAUNCH(false, 16, STV); \
-        else if (ng == 10) SCG_COLS_LAUNCH(false, 10, STV); \
-        else SCG_COLS_LAUNCH(false, 32, STV);               \
+    const bool lr = a.lds_rows > 0 && !learned && (ng == 4 || ng == 8 || ng == 16);
+#define SCG_COLS_LAUNCH(LRN, NGV, STV, LRV) \
+    hipLaunchKernelGGL((cols_kernel<LRN, NGV, STV, LRV>), dim3(grid), dim3(64), lds, s, a)
+#define SCG_COLS_PLAIN(STV)                                  \
+    do {                                                     \
+        if (lr) {                                            \
+            if (ng == 4) SCG_COLS_LAUNCH(false, 4, STV, true);       \
+            else if (ng == 8) SCG_COLS_LAUNCH(false, 8, STV, true);  \
+            else SCG_COLS_LAUNCH(false, 16, STV, true);              \
+        } else if (ng == 4) SCG_COLS_LAUNCH(false, 4, STV, false);   \
+        else if (ng == 8) SCG_COLS_LAUNCH(false, 8, STV, false);     \
+        else if (ng == 16) SCG_COLS_LAUNCH(false, 16, STV, false);   \
+        else if (ng == 10) SCG_COLS_LAUNCH(false, 10, STV, false);   \
+        else SCG_COLS_LAUNCH(false, 32, STV, false);                 \
     } while (0)
     if (learned) {
-        if (ng == 4) SCG_COLS_LAUNCH(true, 4, 0);
-        else if (ng == 8) SCG_COLS_LAUNCH(true, 8, 0);
-        else SCG_COLS_LAUNCH(true, 16, 0);
+        if (ng == 4) SCG_COLS_LAUNCH(true, 4, 0, false);
+        else if (ng == 8) SCG_COLS_LAUNCH(true, 8, 0, false);
+        else SCG_COLS_LAUNCH(true, 16, 0, false);
     } else if (st == 1) {
         SCG_COLS_PLAIN(1);
     } else if (st == 2) {

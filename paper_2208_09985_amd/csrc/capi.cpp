@@ -20,6 +20,8 @@
 struct scg_ctx {
     int device = 0;
     int num_cu = 0;
+    size_t lds_per_cu = 0;          // LDS bytes per CU
+    size_t lds_per_block = 0;       // LDS bytes one workgroup may use
     bool has_model = false;
     int F = 0, H = 0, C = 0;
     __half* model_d = nullptr;      // w1 | b1 | w2 | b2
@@ -61,6 +63,7 @@ struct scg_batch {
     unsigned long long* stats_d = nullptr;
     uint64_t* dent_d = nullptr;     // column-block kernel: stored rows per group
     int dstride = 0;
+    int lds_rows = 0;               // column-block kernel: stored rows kept in LDS
     bool cols = false;              // column-block kernel selected
     bool wide = false;              // windows of 65..128 characters (wide_kernel)
     // launch shape
@@ -115,7 +118,7 @@ int check_params(const scg_params* p) {
     if (p->W < 1 || p->W > 128 || p->O < 0 || p->O >= p->W || p->k < 0 || p->k > p->W) return SCG_EINVAL;
     // windows wider than 64: plain mode in the column-block form only, no yields or ablations
     if (p->W > 64 && (p->mode != SCG_MODE_PLAIN || p->kernel == SCG_KERNEL_ROWS || p->yield_chars > 0 ||
-                      (p->flags & (SCG_FLAG_NO_EARLY_TERMINATION | SCG_FLAG_STORE_ALL_COLUMNS))))
+                      (p->flags & (SCG_FLAG_NO_EARLY_TERMINATION | SCG_FLAG_STORE_ALL_COLUMNS | SCG_FLAG_ROWS_LDS))))
         return SCG_EINVAL;
     if (p->mode < SCG_MODE_PLAIN || p->mode > SCG_MODE_FIXED) return SCG_EINVAL;
     // column blocks without a learned budget also run 32 windows per wavefront
@@ -127,10 +130,9 @@ int check_params(const scg_params* p) {
     if (p->mode == SCG_MODE_LEARNED && !(p->tau > 0.f && p->tau <= 1.f)) return SCG_EINVAL;
     if (p->yield_chars > 0 && p->yield_chars < p->W - p->O) return SCG_EINVAL;
     if (p->kernel < SCG_KERNEL_AUTO || p->kernel > SCG_KERNEL_COLUMNS) return SCG_EINVAL;
-    if (p->flags & ~(SCG_FLAG_GRAPH | SCG_FLAG_NO_EARLY_TERMINATION | SCG_FLAG_STORE_ALL_COLUMNS)) return SCG_EINVAL;
-    if ((p->flags & (SCG_FLAG_NO_EARLY_TERMINATION | SCG_FLAG_STORE_ALL_COLUMNS)) &&
-        (p->mode != SCG_MODE_PLAIN || p->kernel == SCG_KERNEL_ROWS))
-        return SCG_EINVAL;
+    constexpr int32_t kAblations = SCG_FLAG_NO_EARLY_TERMINATION | SCG_FLAG_STORE_ALL_COLUMNS | SCG_FLAG_ROWS_LDS;
+    if (p->flags & ~(SCG_FLAG_GRAPH | kAblations)) return SCG_EINVAL;
+    if ((p->flags & kAblations) && (p->mode != SCG_MODE_PLAIN || p->kernel == SCG_KERNEL_ROWS)) return SCG_EINVAL;
     return SCG_OK;
 }
 
@@ -223,6 +225,7 @@ int enqueue_run(scg_batch* b, hipStream_t s, int32_t* edits, int32_t* text_end, 
     a.stats = b->stats_d;
     a.dent = b->dent_d;
     a.dstride = b->dstride;
+    a.lds_rows = b->lds_rows;
     a.no_et = (b->p.flags & SCG_FLAG_NO_EARLY_TERMINATION) ? 1 : 0;
     if (b->npairs > 0) {
         if (b->wide) HIP_TRY(launch_align_wide(a, b->grid, b->ns, s));
@@ -326,6 +329,9 @@ int scg_create(scg_ctx** out, int device, const char* weights_path) {
     if (!c) return SCG_ENOMEM;
     c->device = device;
     c->num_cu = prop.multiProcessorCount;
+    c->lds_per_cu = prop.maxSharedMemoryPerMultiProcessor ? prop.maxSharedMemoryPerMultiProcessor
+                                                          : prop.sharedMemPerMultiprocessor;
+    c->lds_per_block = prop.sharedMemPerBlock;
     // device address of the allocation-free workspace (looked up once per
     // device; a failure here is reported by scg_align_batch_noalloc itself)
     (void)noalloc_init(device);
@@ -565,8 +571,27 @@ int scg_batch_create(scg_ctx* c, const scg_params* params, int32_t npairs, const
                   : (params->slots <= 10 && !learned) ? 10
                   : params->slots <= 16 ? 16 : 32;
         else b->ns = npairs >= 8 * c->num_cu ? 8 : 4;
+        // SCG_FLAG_ROWS_LDS: the lowest stored rows of each window in LDS, as
+        // many as fit while every wavefront the batch needs (or the
+        // register-limited maximum) stays resident on its CU
+        const int cap = params->W - params->O;
+        const bool lr = (params->flags & SCG_FLAG_ROWS_LDS) && (b->ns == 4 || b->ns == 8 || b->ns == 16);
+        b->lds_rows = 0;
         b->lds = 0;
-        per_cu = cols_max_blocks_per_cu(learned, b->ns, b->lds, params->W - params->O);
+        if (lr) {
+            const int scap = (params->flags & SCG_FLAG_STORE_ALL_COLUMNS) ? 63 : cap;
+            const size_t rowb = (size_t)b->ns * cols_lds_row_bytes(learned, cap, cols_dent_stride(scap, b->ns));
+            int vg = cols_max_blocks_per_cu(learned, b->ns, 0, cap, true);
+            if (params->waves_per_cu > 0) vg = std::min(vg, params->waves_per_cu);
+            const int64_t waves = (npairs + b->ns - 1) / b->ns;
+            const int resident = (int)std::max<int64_t>(1, std::min<int64_t>(vg, (waves + c->num_cu - 1) / c->num_cu));
+            const size_t budget = std::min(c->lds_per_cu / (size_t)resident, c->lds_per_block);
+            const size_t reserve = 2048;   // the kernel's own shared records
+            const int rows = budget > reserve ? (int)((budget - reserve) / rowb) : 0;
+            b->lds_rows = std::min(rows, 64);
+            b->lds = (size_t)b->lds_rows * rowb;
+        }
+        per_cu = cols_max_blocks_per_cu(learned, b->ns, b->lds, cap, b->lds_rows > 0);
     } else {
         b->ns = params->slots > 0 ? params->slots : (params->mode == SCG_MODE_PLAIN ? 1 : 4);
         b->lds = align_lds_bytes(params->W - params->O + 1, b->ns);

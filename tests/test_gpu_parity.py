@@ -152,7 +152,9 @@ def test_ablation_flags_keep_results(ctx, W, O):
     b = synth.make_batch("long_10kbp", indices=range(200, 232))
     ref = oracle.align_batch(b, W, O, W)
     for kw in (dict(no_early_termination=True), dict(store_all_columns=True),
-               dict(no_early_termination=True, store_all_columns=True, slots=4)):
+               dict(no_early_termination=True, store_all_columns=True, slots=4), dict(rows_lds=True),
+               dict(rows_lds=True, store_all_columns=True, slots=16), dict(rows_lds=True, slots=4, waves_per_cu=1),
+               dict(rows_lds=True, no_early_termination=True)):
         log(f"[parity] ablation W={W} O={O} {kw}")
         compare(b, run_gpu(ctx, b, W=W, O=O, k=W, kernel="columns", **kw), ref, f"ablation {kw}")
 
