@@ -92,10 +92,14 @@ enum {
     SCG_FLAG_NO_EARLY_TERMINATION = 2,  /* every window computes all k_w+1 rows (no ET)        */
     SCG_FLAG_STORE_ALL_COLUMNS = 4,     /* store every column of a row, not only 0..W-O (no    */
                                         /* DENT)                                               */
-    SCG_FLAG_ROWS_LDS = 8               /* keep the lowest stored rows of each window in LDS   */
+    SCG_FLAG_ROWS_LDS = 8,              /* keep the lowest stored rows of each window in LDS   */
                                         /* (as many as fit with the wavefronts the batch       */
                                         /* needs; 4, 8 or 16 windows per wavefront), the rest  */
                                         /* in global memory; by default all rows are global    */
+    SCG_FLAG_STORE_EDGES = 16           /* store each entry's edge bitvectors (I, S, D of the  */
+                                        /* row above and M, 32 bytes) instead of the entry (no */
+                                        /* SENE); 4, 8 or 16 windows per wavefront, rows in    */
+                                        /* global memory                                       */
 };
 
 /* which fused kernel aligns the batch (same results, different mappings) */

@@ -22,6 +22,7 @@ FLAG_GRAPH = 1
 FLAG_NO_EARLY_TERMINATION = 2
 FLAG_STORE_ALL_COLUMNS = 4
 FLAG_ROWS_LDS = 8
+FLAG_STORE_EDGES = 16
 KERNEL_AUTO, KERNEL_ROWS, KERNEL_COLUMNS = 0, 1, 2
 NFEATURES = 16
 

@@ -89,6 +89,12 @@ struct GroupRec {      // LDS: what the slot lane tells its group at set-up
 template <bool LEARNED, int NG, int ST, bool LR>
 __global__ __launch_bounds__(64) void cols_kernel(const AlignArgs a) {
     constexpr bool NARROW = ST == 1, SPLIT = ST == 2;
+    // ST 3 (EDGES, the ablation of storing entries instead of edges): every
+    // stored slot holds the three edge bitvectors of Algorithm 1 that the
+    // traceback tests (I, S and D of the row above, from this row) and the
+    // M edge of this row, four 64-bit words, 32 bytes per entry
+    constexpr bool EDGES = ST == 3;
+    constexpr uint32_t EW = EDGES ? 4u : 1u;   // 8-byte words per stored entry
     constexpr int L = 64 / NG;             // lanes per window
     constexpr int CB = cols_per_lane(NG);  // text columns per lane (CB * L >= 64)
     // NG * L < 64 (10 windows of 6 lanes): the lanes past the last group hold
@@ -104,9 +110,9 @@ __global__ __launch_bounds__(64) void cols_kernel(const AlignArgs a) {
     // The block's stored rows start at a wavefront-uniform address; a lane reaches
     // its group's entries with a 32-bit byte offset (a group holds 64 rows of
     // `stride` entries of at most 8 bytes).
-    constexpr uint32_t ESZ = NARROW ? 4u : 8u;   // bytes per stored entry
-    char* const bdent = reinterpret_cast<char*>(a.dent + (size_t)blockIdx.x * NG * (size_t)(kStoredRows * stride));
-    const uint32_t gbyte = (uint32_t)(g * kStoredRows * stride) * 8u;
+    constexpr uint32_t ESZ = NARROW ? 4u : 8u * EW;   // bytes per stored entry
+    char* const bdent = reinterpret_cast<char*>(a.dent + (size_t)blockIdx.x * NG * (size_t)(kStoredRows * stride) * EW);
+    const uint32_t gbyte = (uint32_t)(g * kStoredRows * stride) * 8u * EW;
     const uint32_t qbyte = gbyte + (uint32_t)(CB * q) * ESZ;   // the lane's first column in row 0
     const uint32_t rowbytes = (uint32_t)stride * ESZ;
     // SPLIT: rows of the 32-bit plane (stride*4 bytes) for rows 0..63, then rows
@@ -354,6 +360,22 @@ __global__ __launch_bounds__(64) void cols_kernel(const AlignArgs a) {
                                 for (int t = 0; t < CB / 2; t += 4)
                                     reinterpret_cast<uint4*>(hp)[t >> 2] = uint4{hw[t], hw[t + 1], hw[t + 2], hw[t + 3]};
                             }
+                        } else if (EDGES) {
+                            // slot d: I, S, D of row d+1 (from row d) and M of row d, per column
+                            uint4* row = reinterpret_cast<uint4*>(base + lo_off);
+#pragma unroll
+                            for (int t = 0; t < CB; ++t) {
+                                const uint32_t xl = t + 1 < CB ? A.lo[t + 1] : nlo;   // row d of the next column
+                                const uint32_t xh = t + 1 < CB ? A.hi[t + 1] : nhi;
+                                const uint32_t il = __builtin_amdgcn_alignbit(A.hi[t], A.lo[t], 1);
+                                const uint32_t ih = __builtin_amdgcn_alignbit(1u, A.hi[t], 1);
+                                const uint32_t sl = __builtin_amdgcn_alignbit(xh, xl, 1);
+                                const uint32_t sh = __builtin_amdgcn_alignbit(1u, xh, 1);
+                                const uint32_t ml = sl & E.lo[t];
+                                const uint32_t mh = __builtin_amdgcn_alignbit(tm, xh, 1) & E.hi[t];
+                                row[2 * t] = uint4{il, ih, sl, sh};
+                                row[2 * t + 1] = uint4{xl, xh, ml, mh};
+                            }
                         } else {
                             uint4* row = reinterpret_cast<uint4*>(base + lo_off);
 #pragma unroll
@@ -446,7 +468,7 @@ __global__ __launch_bounds__(64) void cols_kernel(const AlignArgs a) {
                     const int ti = tb_i + L, tj = tb_j + L, td = tb_d;
                     // edit step at (ti, tj, td): bits tj, tj+1 of row td-1 at columns ti and ti+1.
                     // The loads go out first; the run bookkeeping below overlaps them.
-                    uint64_t v0, v1;
+                    uint64_t v0, v1, tb_de = 0;
                     if constexpr (LR) {
                         const uint32_t rr = (uint32_t)(max(td, 1) - 1);
                         const uint32_t c0 = (uint32_t)min(ti, stride - 1), c1 = (uint32_t)min(ti + 1, stride - 1);
@@ -493,6 +515,15 @@ __global__ __launch_bounds__(64) void cols_kernel(const AlignArgs a) {
                             v0 = lw;
                             v1 = hw;
                         }
+                    } else if constexpr (EDGES) {
+                        // the edges of entry (ti, td): slot td-1 of column ti, I and S in the
+                        // first 16 bytes, D (and M) in the second
+                        const uint32_t ro = gbyte + __umul24((uint32_t)(max(td, 1) - 1), rowbytes);
+                        const uint4* const e = reinterpret_cast<const uint4*>(bdent + (ro + (uint32_t)min(ti, stride - 1) * ESZ));
+                        const uint4 is = e[0], dm = e[1];
+                        v0 = (uint64_t)is.y << 32 | is.x;   // I edge
+                        v1 = (uint64_t)is.w << 32 | is.z;   // S edge
+                        tb_de = (uint64_t)dm.y << 32 | dm.x;   // D edge
                     } else {
                         const uint32_t ro = gbyte + __umul24((uint32_t)(max(td, 1) - 1), rowbytes);
                         const char* const e0 = bdent + (ro + (uint32_t)min(ti, stride - 1) * ESZ);
@@ -526,15 +557,23 @@ __global__ __launch_bounds__(64) void cols_kernel(const AlignArgs a) {
                         rout[(uint32_t)min(nruns, rlast)] = ((uint32_t)cur_len << 2) | (uint32_t)cur_op;
                     }
                     const bool edit = !(tj >= jlim || ti >= cap);
-                    const uint64_t za = ti < nw ? v0 : tb_rc;        // Z[ti][td-1]
-                    const uint64_t zb = ti + 1 < nw ? v1 : tb_rc;    // Z[ti+1][td-1]
                     const int has_t = ti < nw;
-                    // bits tj and tj+1 (tj <= 63 in an edit step; bit 64 is the implicit set bit)
-                    const uint64_t sa = za >> (tj & 63), sz = zb >> (tj & 63);
-                    const int top = tj >= 63 ? 1 : 0;
-                    const int sb = has_t & (((int)(sz >> 1) & 1) | top);
-                    const int ib = ((int)(sa >> 1) & 1) | top;
-                    const int db = has_t & (int)(sz & 1);
+                    int sb, ib, db;
+                    if constexpr (EDGES) {
+                        // the stored edges, bit tj (their bit 63 is the shifted-in 1)
+                        sb = has_t & (int)((v1 >> (tj & 63)) & 1ull);
+                        ib = (int)((v0 >> (tj & 63)) & 1ull);
+                        db = has_t & (int)((tb_de >> (tj & 63)) & 1ull);
+                    } else {
+                        const uint64_t za = ti < nw ? v0 : tb_rc;        // Z[ti][td-1]
+                        const uint64_t zb = ti + 1 < nw ? v1 : tb_rc;    // Z[ti+1][td-1]
+                        // bits tj and tj+1 (tj <= 63 in an edit step; bit 64 is the implicit set bit)
+                        const uint64_t sa = za >> (tj & 63), sz = zb >> (tj & 63);
+                        const int top = tj >= 63 ? 1 : 0;
+                        sb = has_t & (((int)(sz >> 1) & 1) | top);
+                        ib = ((int)(sa >> 1) & 1) | top;
+                        db = has_t & (int)(sz & 1);
+                    }
                     const int op = sb ? 1 : (ib ? 2 : 3);
                     tb_bad |= edit & ((td <= 0) | !(sb | ib | db));
                     tb_i = ti + (edit && op != 2 ? 1 : 0);
@@ -615,8 +654,8 @@ int cols_dent_stride(int cap, int ng) {
     return (cols + cb - 1) / cb * cb;               // whole lanes of CB columns
 }
 
-size_t cols_dent_bytes(int grid, int cap, int ng) {
-    return (size_t)grid * ng * kStoredRows * (size_t)cols_dent_stride(cap, ng) * sizeof(uint64_t);
+size_t cols_dent_bytes(int grid, int cap, int ng, bool edges) {
+    return (size_t)grid * ng * kStoredRows * (size_t)cols_dent_stride(cap, ng) * sizeof(uint64_t) * (edges ? 4 : 1);
 }
 
 // 32-bit stored entries when traceback reads bits 0..31 at most, 48-bit ones
@@ -656,10 +695,18 @@ static const void* cols_fn_plain(int ng, bool lds_rows) {
     return cols_fn<false, ST>(ng);
 }
 
-int cols_max_blocks_per_cu(bool learned, int ng, size_t lds, int cap, bool lds_rows) {
+// the edge-storing ablation form: plain mode, 4, 8 or 16 windows per wavefront
+static const void* cols_fn_edges(int ng) {
+    if (ng == 4) return (const void*)cols_kernel<false, 4, 3, false>;
+    if (ng == 8) return (const void*)cols_kernel<false, 8, 3, false>;
+    return (const void*)cols_kernel<false, 16, 3, false>;
+}
+
+int cols_max_blocks_per_cu(bool learned, int ng, size_t lds, int cap, bool lds_rows, bool edges) {
     int nb = 0;
     const int st = cols_store(learned, cap);
     const void* f = learned ? cols_fn<true, 0>(ng)
+                  : edges ? cols_fn_edges(ng)
                   : (st == 1 ? cols_fn_plain<1>(ng, lds_rows)
                              : (st == 2 ? cols_fn_plain<2>(ng, lds_rows) : cols_fn_plain<0>(ng, lds_rows)));
     if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, f, 64, lds) != hipSuccess) return 1;
@@ -684,7 +731,11 @@ hipError_t launch_align_cols(const AlignArgs& a, int grid, int ng, size_t lds, h
         else if (ng == 10) SCG_COLS_LAUNCH(false, 10, STV, false);   \
         else SCG_COLS_LAUNCH(false, 32, STV, false);                 \
     } while (0)
-    if (learned) {
+    if (a.edges) {
+        if (ng == 4) SCG_COLS_LAUNCH(false, 4, 3, false);
+        else if (ng == 8) SCG_COLS_LAUNCH(false, 8, 3, false);
+        else SCG_COLS_LAUNCH(false, 16, 3, false);
+    } else if (learned) {
         if (ng == 4) SCG_COLS_LAUNCH(true, 4, 0, false);
         else if (ng == 8) SCG_COLS_LAUNCH(true, 8, 0, false);
         else SCG_COLS_LAUNCH(true, 16, 0, false);

@@ -118,7 +118,8 @@ int check_params(const scg_params* p) {
     if (p->W < 1 || p->W > 128 || p->O < 0 || p->O >= p->W || p->k < 0 || p->k > p->W) return SCG_EINVAL;
     // windows wider than 64: plain mode in the column-block form only, no yields or ablations
     if (p->W > 64 && (p->mode != SCG_MODE_PLAIN || p->kernel == SCG_KERNEL_ROWS || p->yield_chars > 0 ||
-                      (p->flags & (SCG_FLAG_NO_EARLY_TERMINATION | SCG_FLAG_STORE_ALL_COLUMNS | SCG_FLAG_ROWS_LDS))))
+                      (p->flags & (SCG_FLAG_NO_EARLY_TERMINATION | SCG_FLAG_STORE_ALL_COLUMNS | SCG_FLAG_ROWS_LDS |
+                                   SCG_FLAG_STORE_EDGES))))
         return SCG_EINVAL;
     if (p->mode < SCG_MODE_PLAIN || p->mode > SCG_MODE_FIXED) return SCG_EINVAL;
     // column blocks without a learned budget also run 32 windows per wavefront
@@ -130,9 +131,14 @@ int check_params(const scg_params* p) {
     if (p->mode == SCG_MODE_LEARNED && !(p->tau > 0.f && p->tau <= 1.f)) return SCG_EINVAL;
     if (p->yield_chars > 0 && p->yield_chars < p->W - p->O) return SCG_EINVAL;
     if (p->kernel < SCG_KERNEL_AUTO || p->kernel > SCG_KERNEL_COLUMNS) return SCG_EINVAL;
-    constexpr int32_t kAblations = SCG_FLAG_NO_EARLY_TERMINATION | SCG_FLAG_STORE_ALL_COLUMNS | SCG_FLAG_ROWS_LDS;
+    constexpr int32_t kAblations =
+        SCG_FLAG_NO_EARLY_TERMINATION | SCG_FLAG_STORE_ALL_COLUMNS | SCG_FLAG_ROWS_LDS | SCG_FLAG_STORE_EDGES;
     if (p->flags & ~(SCG_FLAG_GRAPH | kAblations)) return SCG_EINVAL;
     if ((p->flags & kAblations) && (p->mode != SCG_MODE_PLAIN || p->kernel == SCG_KERNEL_ROWS)) return SCG_EINVAL;
+    // edges are stored as whole 64-bit words, in global memory, with 4, 8 or 16 windows per wavefront
+    if ((p->flags & SCG_FLAG_STORE_EDGES) && ((p->flags & SCG_FLAG_ROWS_LDS) || (p->slots > 16 && p->slots != 0) ||
+                                               (p->slots > 8 && p->slots <= 10)))
+        return SCG_EINVAL;
     return SCG_OK;
 }
 
@@ -226,6 +232,7 @@ int enqueue_run(scg_batch* b, hipStream_t s, int32_t* edits, int32_t* text_end, 
     a.dent = b->dent_d;
     a.dstride = b->dstride;
     a.lds_rows = b->lds_rows;
+    a.edges = (b->p.flags & SCG_FLAG_STORE_EDGES) ? 1 : 0;
     a.no_et = (b->p.flags & SCG_FLAG_NO_EARLY_TERMINATION) ? 1 : 0;
     if (b->npairs > 0) {
         if (b->wide) HIP_TRY(launch_align_wide(a, b->grid, b->ns, s));
@@ -575,13 +582,14 @@ int scg_batch_create(scg_ctx* c, const scg_params* params, int32_t npairs, const
         // many as fit while every wavefront the batch needs (or the
         // register-limited maximum) stays resident on its CU
         const int cap = params->W - params->O;
+        const bool edges = (params->flags & SCG_FLAG_STORE_EDGES) != 0;
         const bool lr = (params->flags & SCG_FLAG_ROWS_LDS) && (b->ns == 4 || b->ns == 8 || b->ns == 16);
         b->lds_rows = 0;
         b->lds = 0;
         if (lr) {
             const int scap = (params->flags & SCG_FLAG_STORE_ALL_COLUMNS) ? 63 : cap;
             const size_t rowb = (size_t)b->ns * cols_lds_row_bytes(learned, cap, cols_dent_stride(scap, b->ns));
-            int vg = cols_max_blocks_per_cu(learned, b->ns, 0, cap, true);
+            int vg = cols_max_blocks_per_cu(learned, b->ns, 0, cap, true, false);
             if (params->waves_per_cu > 0) vg = std::min(vg, params->waves_per_cu);
             const int64_t waves = (npairs + b->ns - 1) / b->ns;
             const int resident = (int)std::max<int64_t>(1, std::min<int64_t>(vg, (waves + c->num_cu - 1) / c->num_cu));
@@ -591,7 +599,7 @@ int scg_batch_create(scg_ctx* c, const scg_params* params, int32_t npairs, const
             b->lds_rows = std::min(rows, 64);
             b->lds = (size_t)b->lds_rows * rowb;
         }
-        per_cu = cols_max_blocks_per_cu(learned, b->ns, b->lds, cap, b->lds_rows > 0);
+        per_cu = cols_max_blocks_per_cu(learned, b->ns, b->lds, cap, b->lds_rows > 0, edges);
     } else {
         b->ns = params->slots > 0 ? params->slots : (params->mode == SCG_MODE_PLAIN ? 1 : 4);
         b->lds = align_lds_bytes(params->W - params->O + 1, b->ns);
@@ -611,7 +619,8 @@ int scg_batch_create(scg_ctx* c, const scg_params* params, int32_t npairs, const
         // stored columns 0..cap (DENT), or all of them for the ablation
         const int scap = (params->flags & SCG_FLAG_STORE_ALL_COLUMNS) ? 63 : cap;
         b->dstride = cols_dent_stride(scap, b->ns);
-        if ((rc = dev_alloc(&b->dent_d, cols_dent_bytes(b->grid, scap, b->ns) / sizeof(uint64_t)))) return fail(rc);
+        const bool edges = (params->flags & SCG_FLAG_STORE_EDGES) != 0;
+        if ((rc = dev_alloc(&b->dent_d, cols_dent_bytes(b->grid, scap, b->ns, edges) / sizeof(uint64_t)))) return fail(rc);
     }
     *out = b;
     return SCG_OK;

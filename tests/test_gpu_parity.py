@@ -98,6 +98,7 @@ def test_window_parameters(ctx, W, O, k):
     check(ctx, b, W=W, O=O, k=k, what=f"W{W}O{O}k{k}")
     check(ctx, b, W=W, O=O, k=k, mode="fixed", fixed_rows=3, what=f"W{W}O{O}k{k} fixed3")
     check(ctx, b, W=W, O=O, k=k, what=f"W{W}O{O}k{k} 10 windows per wavefront", kernels=("columns",), slots=10)
+    check(ctx, b, W=W, O=O, k=k, what=f"W{W}O{O}k{k} edges stored", kernels=("columns",), store_edges=True)
 
 
 def test_edge_cases(ctx):
@@ -108,6 +109,8 @@ def test_edge_cases(ctx):
     b = synth.from_lists(pats, txts)
     check(ctx, b, what="edge cases")
     check(ctx, b, k=5, what="edge cases k=5 (not aligned)")
+    check(ctx, b, what="edge cases, edges stored", kernels=("columns",), store_edges=True)
+    check(ctx, b, what="edge cases, rows in LDS", kernels=("columns",), rows_lds=True)
 
 
 def test_bad_device_input_marks_pair(ctx):
@@ -154,7 +157,9 @@ def test_ablation_flags_keep_results(ctx, W, O):
     for kw in (dict(no_early_termination=True), dict(store_all_columns=True),
                dict(no_early_termination=True, store_all_columns=True, slots=4), dict(rows_lds=True),
                dict(rows_lds=True, store_all_columns=True, slots=16), dict(rows_lds=True, slots=4, waves_per_cu=1),
-               dict(rows_lds=True, no_early_termination=True)):
+               dict(rows_lds=True, no_early_termination=True), dict(store_edges=True),
+               dict(store_edges=True, no_early_termination=True, store_all_columns=True, slots=4),
+               dict(store_edges=True, slots=16)):
         log(f"[parity] ablation W={W} O={O} {kw}")
         compare(b, run_gpu(ctx, b, W=W, O=O, k=W, kernel="columns", **kw), ref, f"ablation {kw}")
 
@@ -203,6 +208,8 @@ def test_unrelated_pairs_long_tracebacks(ctx):
     b = synth.from_lists(pats, txts)
     for slots in (4, 8, 10, 16):
         check(ctx, b, what=f"unrelated slots={slots}", kernels=("columns",), slots=slots)
+    check(ctx, b, what="unrelated, edges stored", kernels=("columns",), store_edges=True)
+    check(ctx, b, what="unrelated, rows in LDS", kernels=("columns",), rows_lds=True)
     check(ctx, b, what="unrelated rows", kernels=("rows",))
 
 
