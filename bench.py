@@ -323,16 +323,31 @@ def main():
             e["lanes_per_window"] = 64 // ng
             lanes[f"windows_per_wavefront_{ng}"] = e
         workloads["column_blocks_long_10kbp"] = lanes
-        # the paper's improvements switched off one at a time in the default kernel (same alignments)
+        # the paper's three improvements (SENE: entries, not edges; DENT: only the columns traceback
+        # reads; ET: rows stop at d_w) switched off in every combination, with the stored rows in global
+        # memory (default) or the lowest rows in LDS, at W=64 with O=24 (the headline) and O=33
+        # (32-bit entries); every combination gives the same alignments
         abl = {}
-        for tag, kw in (("all_on", {}), ("no_early_termination", dict(no_early_termination=True)),
-                        ("store_all_columns", dict(store_all_columns=True)),
-                        ("neither", dict(no_early_termination=True, store_all_columns=True))):
-            ams, ast, ares = measure(batch, f"ablation {tag}",
-                                     api.params(W=w.W, O=w.O, k=w.k, mode="plain", kernel="columns", **kw), 5, 1)
-            e = summary(batch, ams, ast, same_output(ares, res))
-            e["rows_computed"] = int(ast.rows_budgeted)
-            abl[tag] = e
+        for (W, O) in ((64, 24), (64, 33)):
+            ref_res = None
+            for sene in (True, False):
+                for dent in (True, False):
+                    for et in (True, False):
+                        for lds in ((False, True) if sene else (False,)):
+                            on = "+".join(x for x, f in (("SENE", sene), ("DENT", dent), ("ET", et)) if f) or "none"
+                            tag = f"W{W}_O{O}_{on}" + ("_lds" if lds else "")
+                            kw = dict(no_early_termination=not et, store_all_columns=not dent, store_edges=not sene,
+                                      rows_lds=lds)
+                            steps_ = 5 if (sene and et) else 2
+                            ams, ast, ares = measure(batch, f"ablation {tag}",
+                                                     api.params(W=W, O=O, k=W, mode="plain", kernel="columns", **kw),
+                                                     steps_, 1)
+                            if ref_res is None:
+                                ref_res = ares
+                            e = summary(batch, ams, ast, same_output(ares, ref_res))
+                            e.update(rows_computed=int(ast.rows_budgeted), sene=sene, dent=dent, et=et,
+                                     stored_rows="lds+global" if lds else "global")
+                            abl[tag] = e
         workloads["ablation_long_10kbp"] = abl
         # more pairs of the headline shape: how far latency hiding goes once the GPU holds more wavefronts
         scale = {}

@@ -96,10 +96,15 @@ enum {
                                         /* (as many as fit with the wavefronts the batch       */
                                         /* needs; 4, 8 or 16 windows per wavefront), the rest  */
                                         /* in global memory; by default all rows are global    */
-    SCG_FLAG_STORE_EDGES = 16           /* store each entry's edge bitvectors (I, S, D of the  */
+    SCG_FLAG_STORE_EDGES = 16,          /* store each entry's edge bitvectors (I, S, D of the  */
                                         /* row above and M, 32 bytes) instead of the entry (no */
                                         /* SENE); 4, 8 or 16 windows per wavefront, rows in    */
                                         /* global memory                                       */
+    SCG_FLAG_ROW_RING = 32              /* DENT extended to rows (supplementary Section 1):    */
+                                        /* stored rows in a ring of W-O+1+64/slots slots, the  */
+                                        /* rows traceback can read below d_w plus those the    */
+                                        /* lanes compute past it; needs early termination; 4,  */
+                                        /* 8 or 16 windows per wavefront                       */
 };
 
 /* which fused kernel aligns the batch (same results, different mappings) */

@@ -34,7 +34,7 @@ def _stream_ptr(stream) -> ctypes.c_void_p:
 
 def params(W=64, O=24, k=64, mode="plain", slots=0, waves_per_cu=0, order="input", fixed_rows=None, tau=None,
            graph=False, yield_chars=None, kernel="auto", no_early_termination=False,
-           store_all_columns=False, rows_lds=False, store_edges=False) -> L.Params:
+           store_all_columns=False, rows_lds=False, store_edges=False, row_ring=False) -> L.Params:
     p = L.Params()
     L.load().scg_params_default(ctypes.byref(p))
     p.W, p.O, p.k = W, O, k
@@ -47,7 +47,7 @@ def params(W=64, O=24, k=64, mode="plain", slots=0, waves_per_cu=0, order="input
         p.tau = tau
     p.flags = ((L.FLAG_GRAPH if graph else 0) | (L.FLAG_NO_EARLY_TERMINATION if no_early_termination else 0)
                | (L.FLAG_STORE_ALL_COLUMNS if store_all_columns else 0) | (L.FLAG_ROWS_LDS if rows_lds else 0)
-               | (L.FLAG_STORE_EDGES if store_edges else 0))
+               | (L.FLAG_STORE_EDGES if store_edges else 0) | (L.FLAG_ROW_RING if row_ring else 0))
     if yield_chars is not None:
         p.yield_chars = yield_chars
     p.kernel = {"auto": L.KERNEL_AUTO, "rows": L.KERNEL_ROWS, "columns": L.KERNEL_COLUMNS}[kernel]

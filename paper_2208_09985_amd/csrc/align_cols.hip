@@ -86,8 +86,13 @@ struct GroupRec {      // LDS: what the slot lane tells its group at set-up
 // ST: the stored entries.  0: whole 64-bit entries.  1 (NARROW): their low 32
 // bits, when traceback reads bits 0..31 at most.  2 (SPLIT): their low 48 bits
 // as a 32-bit plane and a 16-bit plane, when it reads bits 0..47 at most.
-template <bool LEARNED, int NG, int ST, bool LR>
+// SM: where the stored rows go.  0: rows 0..63 in the global region.  1: the
+// lowest lds_rows rows in LDS, the others global.  2 (DENT extended to rows,
+// supplementary Section 1): a ring of ring_rows slots in the global region,
+// row d in slot d mod ring_rows.
+template <bool LEARNED, int NG, int ST, int SM>
 __global__ __launch_bounds__(64) void cols_kernel(const AlignArgs a) {
+    constexpr bool LR = SM == 1, RING = SM == 2;
     constexpr bool NARROW = ST == 1, SPLIT = ST == 2;
     // ST 3 (EDGES, the ablation of storing entries instead of edges): every
     // stored slot holds the three edge bitvectors of Algorithm 1 that the
@@ -111,14 +116,24 @@ __global__ __launch_bounds__(64) void cols_kernel(const AlignArgs a) {
     // its group's entries with a 32-bit byte offset (a group holds 64 rows of
     // `stride` entries of at most 8 bytes).
     constexpr uint32_t ESZ = NARROW ? 4u : 8u * EW;   // bytes per stored entry
-    char* const bdent = reinterpret_cast<char*>(a.dent + (size_t)blockIdx.x * NG * (size_t)(kStoredRows * stride) * EW);
-    const uint32_t gbyte = (uint32_t)(g * kStoredRows * stride) * 8u * EW;
+    // rows per group in the global region: 64, or the ring's slots
+    const int NR = RING ? a.ring_rows : kStoredRows;
+    const uint32_t NRu = (uint32_t)NR;
+    char* const bdent = reinterpret_cast<char*>(a.dent + (size_t)blockIdx.x * NG * (size_t)(NR * stride) * EW);
+    const uint32_t gbyte = (uint32_t)(g * NR * stride) * 8u * EW;
+    // the slot of stored row r (a ring when RING: rows of one window never need
+    // more than ring_rows consecutive slots)
+    auto slot_of = [&](uint32_t r) -> uint32_t {
+        if (!RING) return r;
+        uint32_t sl = r >= NRu ? r - NRu : r;
+        return sl >= NRu ? r % NRu : sl;
+    };
     const uint32_t qbyte = gbyte + (uint32_t)(CB * q) * ESZ;   // the lane's first column in row 0
     const uint32_t rowbytes = (uint32_t)stride * ESZ;
     // SPLIT: rows of the 32-bit plane (stride*4 bytes) for rows 0..63, then rows
     // of the 16-bit plane (stride*2 bytes)
     const uint32_t lobytes = (uint32_t)stride * 4u, hibytes = (uint32_t)stride * 2u;
-    const uint32_t hiplane = gbyte + (uint32_t)kStoredRows * lobytes;
+    const uint32_t hiplane = gbyte + NRu * lobytes;
     const bool storer = CB * q < stride;
     // Rows 0..R-1 of every group's stored region live in LDS (dynamic shared
     // memory, R chosen by the host from the occupancy the batch needs): the
@@ -387,8 +402,11 @@ __global__ __launch_bounds__(64) void cols_kernel(const AlignArgs a) {
                         put(lrows, lgbyte + udh * (SPLIT ? lobytes : rowbytes) + (uint32_t)(CB * q) * (SPLIT ? 4u : ESZ),
                             lhiplane + udh * hibytes + (uint32_t)(CB * q) * 2u);
                     } else {
-                        put(bdent, SPLIT ? gbyte + __umul24(udh, lobytes) + (uint32_t)(CB * q) * 4u : soff + (h ? rowbytes : 0u),
-                            hiplane + __umul24(udh, hibytes) + (uint32_t)(CB * q) * 2u);
+                        const uint32_t sl = slot_of(udh);
+                        put(bdent,
+                            SPLIT ? gbyte + __umul24(sl, lobytes) + (uint32_t)(CB * q) * 4u
+                                  : (RING ? qbyte + __umul24(sl, rowbytes) : soff + (h ? rowbytes : 0u)),
+                            hiplane + __umul24(sl, hibytes) + (uint32_t)(CB * q) * 2u);
                     }
                 }
                 // early termination: column 0 of row d has the msb of R clear.  Lane 0 of
@@ -518,14 +536,14 @@ __global__ __launch_bounds__(64) void cols_kernel(const AlignArgs a) {
                     } else if constexpr (EDGES) {
                         // the edges of entry (ti, td): slot td-1 of column ti, I and S in the
                         // first 16 bytes, D (and M) in the second
-                        const uint32_t ro = gbyte + __umul24((uint32_t)(max(td, 1) - 1), rowbytes);
+                        const uint32_t ro = gbyte + __umul24(slot_of((uint32_t)(max(td, 1) - 1)), rowbytes);
                         const uint4* const e = reinterpret_cast<const uint4*>(bdent + (ro + (uint32_t)min(ti, stride - 1) * ESZ));
                         const uint4 is = e[0], dm = e[1];
                         v0 = (uint64_t)is.y << 32 | is.x;   // I edge
                         v1 = (uint64_t)is.w << 32 | is.z;   // S edge
                         tb_de = (uint64_t)dm.y << 32 | dm.x;   // D edge
                     } else {
-                        const uint32_t ro = gbyte + __umul24((uint32_t)(max(td, 1) - 1), rowbytes);
+                        const uint32_t ro = gbyte + __umul24(slot_of((uint32_t)(max(td, 1) - 1)), rowbytes);
                         const char* const e0 = bdent + (ro + (uint32_t)min(ti, stride - 1) * ESZ);
                         const char* const e1 = bdent + (ro + (uint32_t)min(ti + 1, stride - 1) * ESZ);
                         if (NARROW) {
@@ -535,7 +553,7 @@ __global__ __launch_bounds__(64) void cols_kernel(const AlignArgs a) {
                             // columns ti and ti+1 of both planes, as one 8-byte word each (the
                             // 16-bit word from the 4-byte boundary at or below column ti)
                             struct __attribute__((packed, aligned(4))) W2 { uint64_t v; };
-                            const uint32_t rr = (uint32_t)(max(td, 1) - 1);
+                            const uint32_t rr = slot_of((uint32_t)(max(td, 1) - 1));
                             const uint32_t c0 = (uint32_t)min(ti, stride - 1);
                             const uint64_t lw = reinterpret_cast<const W2*>(bdent + (gbyte + __umul24(rr, lobytes) + c0 * 4u))->v;
                             const uint64_t hw = reinterpret_cast<const W2*>(bdent + (hiplane + __umul24(rr, hibytes) + (c0 & ~1u) * 2u))->v
@@ -654,8 +672,9 @@ int cols_dent_stride(int cap, int ng) {
     return (cols + cb - 1) / cb * cb;               // whole lanes of CB columns
 }
 
-size_t cols_dent_bytes(int grid, int cap, int ng, bool edges) {
-    return (size_t)grid * ng * kStoredRows * (size_t)cols_dent_stride(cap, ng) * sizeof(uint64_t) * (edges ? 4 : 1);
+size_t cols_dent_bytes(int grid, int cap, int ng, bool edges, int ring_rows) {
+    const int rows = ring_rows > 0 ? ring_rows : kStoredRows;
+    return (size_t)grid * ng * rows * (size_t)cols_dent_stride(cap, ng) * sizeof(uint64_t) * (edges ? 4 : 1);
 }
 
 // 32-bit stored entries when traceback reads bits 0..31 at most, 48-bit ones
@@ -672,9 +691,9 @@ size_t cols_lds_row_bytes(bool learned, int cap, int stride) {
 template <bool LEARNED, int ST>
 static const void* cols_fn(int ng) {
     switch (ng) {
-    case 4: return (const void*)cols_kernel<LEARNED, 4, ST, false>;
-    case 8: return (const void*)cols_kernel<LEARNED, 8, ST, false>;
-    default: return (const void*)cols_kernel<LEARNED, 16, ST, false>;
+    case 4: return (const void*)cols_kernel<LEARNED, 4, ST, 0>;
+    case 8: return (const void*)cols_kernel<LEARNED, 8, ST, 0>;
+    default: return (const void*)cols_kernel<LEARNED, 16, ST, 0>;
     }
 }
 
@@ -684,31 +703,41 @@ static const void* cols_fn(int ng) {
 // ten pairs per SIMD; and, with 4, 8 or 16 windows, the form that keeps the
 // lowest stored rows in LDS
 template <int ST>
-static const void* cols_fn_plain(int ng, bool lds_rows) {
-    if (lds_rows) {
-        if (ng == 4) return (const void*)cols_kernel<false, 4, ST, true>;
-        if (ng == 8) return (const void*)cols_kernel<false, 8, ST, true>;
-        return (const void*)cols_kernel<false, 16, ST, true>;
+static const void* cols_fn_plain(int ng, int sm) {
+    if (sm == 1) {
+        if (ng == 4) return (const void*)cols_kernel<false, 4, ST, 1>;
+        if (ng == 8) return (const void*)cols_kernel<false, 8, ST, 1>;
+        return (const void*)cols_kernel<false, 16, ST, 1>;
     }
-    if (ng == 32) return (const void*)cols_kernel<false, 32, ST, false>;
-    if (ng == 10) return (const void*)cols_kernel<false, 10, ST, false>;
+    if (sm == 2) {
+        if (ng == 4) return (const void*)cols_kernel<false, 4, ST, 2>;
+        if (ng == 8) return (const void*)cols_kernel<false, 8, ST, 2>;
+        return (const void*)cols_kernel<false, 16, ST, 2>;
+    }
+    if (ng == 32) return (const void*)cols_kernel<false, 32, ST, 0>;
+    if (ng == 10) return (const void*)cols_kernel<false, 10, ST, 0>;
     return cols_fn<false, ST>(ng);
 }
 
 // the edge-storing ablation form: plain mode, 4, 8 or 16 windows per wavefront
-static const void* cols_fn_edges(int ng) {
-    if (ng == 4) return (const void*)cols_kernel<false, 4, 3, false>;
-    if (ng == 8) return (const void*)cols_kernel<false, 8, 3, false>;
-    return (const void*)cols_kernel<false, 16, 3, false>;
+static const void* cols_fn_edges(int ng, int sm) {
+    if (sm == 2) {
+        if (ng == 4) return (const void*)cols_kernel<false, 4, 3, 2>;
+        if (ng == 8) return (const void*)cols_kernel<false, 8, 3, 2>;
+        return (const void*)cols_kernel<false, 16, 3, 2>;
+    }
+    if (ng == 4) return (const void*)cols_kernel<false, 4, 3, 0>;
+    if (ng == 8) return (const void*)cols_kernel<false, 8, 3, 0>;
+    return (const void*)cols_kernel<false, 16, 3, 0>;
 }
 
-int cols_max_blocks_per_cu(bool learned, int ng, size_t lds, int cap, bool lds_rows, bool edges) {
+int cols_max_blocks_per_cu(bool learned, int ng, size_t lds, int cap, int sm, bool edges) {
     int nb = 0;
     const int st = cols_store(learned, cap);
     const void* f = learned ? cols_fn<true, 0>(ng)
-                  : edges ? cols_fn_edges(ng)
-                  : (st == 1 ? cols_fn_plain<1>(ng, lds_rows)
-                             : (st == 2 ? cols_fn_plain<2>(ng, lds_rows) : cols_fn_plain<0>(ng, lds_rows)));
+                  : edges ? cols_fn_edges(ng, sm == 2 ? 2 : 0)
+                  : (st == 1 ? cols_fn_plain<1>(ng, sm)
+                             : (st == 2 ? cols_fn_plain<2>(ng, sm) : cols_fn_plain<0>(ng, sm)));
     if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, f, 64, lds) != hipSuccess) return 1;
     return nb < 1 ? 1 : nb;
 }
@@ -716,29 +745,43 @@ int cols_max_blocks_per_cu(bool learned, int ng, size_t lds, int cap, bool lds_r
 hipError_t launch_align_cols(const AlignArgs& a, int grid, int ng, size_t lds, hipStream_t s) {
     const bool learned = a.mode == 1;
     const int st = cols_store(learned, a.cap);
-    const bool lr = a.lds_rows > 0 && !learned && (ng == 4 || ng == 8 || ng == 16);
+    const bool small = ng == 4 || ng == 8 || ng == 16;
+    const int sm = learned || !small ? 0 : (a.lds_rows > 0 ? 1 : (a.ring_rows > 0 ? 2 : 0));
+    // the host sized the stored-row region for the ring (or the LDS rows): every
+    // launch below must use that layout, so a combination without one is refused
+    if ((a.ring_rows > 0 || a.lds_rows > 0) && (learned || !small)) return hipErrorInvalidValue;
+    if (a.edges && a.lds_rows > 0) return hipErrorInvalidValue;
 #define SCG_COLS_LAUNCH(LRN, NGV, STV, LRV) \
     hipLaunchKernelGGL((cols_kernel<LRN, NGV, STV, LRV>), dim3(grid), dim3(64), lds, s, a)
 #define SCG_COLS_PLAIN(STV)                                  \
     do {                                                     \
-        if (lr) {                                            \
-            if (ng == 4) SCG_COLS_LAUNCH(false, 4, STV, true);       \
-            else if (ng == 8) SCG_COLS_LAUNCH(false, 8, STV, true);  \
-            else SCG_COLS_LAUNCH(false, 16, STV, true);              \
-        } else if (ng == 4) SCG_COLS_LAUNCH(false, 4, STV, false);   \
-        else if (ng == 8) SCG_COLS_LAUNCH(false, 8, STV, false);     \
-        else if (ng == 16) SCG_COLS_LAUNCH(false, 16, STV, false);   \
-        else if (ng == 10) SCG_COLS_LAUNCH(false, 10, STV, false);   \
-        else SCG_COLS_LAUNCH(false, 32, STV, false);                 \
+        if (sm == 1) {                                       \
+            if (ng == 4) SCG_COLS_LAUNCH(false, 4, STV, 1);          \
+            else if (ng == 8) SCG_COLS_LAUNCH(false, 8, STV, 1);     \
+            else SCG_COLS_LAUNCH(false, 16, STV, 1);                 \
+        } else if (sm == 2) {                                \
+            if (ng == 4) SCG_COLS_LAUNCH(false, 4, STV, 2);          \
+            else if (ng == 8) SCG_COLS_LAUNCH(false, 8, STV, 2);     \
+            else SCG_COLS_LAUNCH(false, 16, STV, 2);                 \
+        } else if (ng == 4) SCG_COLS_LAUNCH(false, 4, STV, 0);       \
+        else if (ng == 8) SCG_COLS_LAUNCH(false, 8, STV, 0);         \
+        else if (ng == 16) SCG_COLS_LAUNCH(false, 16, STV, 0);       \
+        else if (ng == 10) SCG_COLS_LAUNCH(false, 10, STV, 0);       \
+        else SCG_COLS_LAUNCH(false, 32, STV, 0);                     \
     } while (0)
     if (a.edges) {
-        if (ng == 4) SCG_COLS_LAUNCH(false, 4, 3, false);
-        else if (ng == 8) SCG_COLS_LAUNCH(false, 8, 3, false);
-        else SCG_COLS_LAUNCH(false, 16, 3, false);
+        // the stored-row layout (64 rows or the ring) must be the one the host allocated
+        if (sm == 2) {
+            if (ng == 4) SCG_COLS_LAUNCH(false, 4, 3, 2);
+            else if (ng == 8) SCG_COLS_LAUNCH(false, 8, 3, 2);
+            else SCG_COLS_LAUNCH(false, 16, 3, 2);
+        } else if (ng == 4) SCG_COLS_LAUNCH(false, 4, 3, 0);
+        else if (ng == 8) SCG_COLS_LAUNCH(false, 8, 3, 0);
+        else SCG_COLS_LAUNCH(false, 16, 3, 0);
     } else if (learned) {
-        if (ng == 4) SCG_COLS_LAUNCH(true, 4, 0, false);
-        else if (ng == 8) SCG_COLS_LAUNCH(true, 8, 0, false);
-        else SCG_COLS_LAUNCH(true, 16, 0, false);
+        if (ng == 4) SCG_COLS_LAUNCH(true, 4, 0, 0);
+        else if (ng == 8) SCG_COLS_LAUNCH(true, 8, 0, 0);
+        else SCG_COLS_LAUNCH(true, 16, 0, 0);
     } else if (st == 1) {
         SCG_COLS_PLAIN(1);
     } else if (st == 2) {

@@ -64,6 +64,7 @@ struct scg_batch {
     uint64_t* dent_d = nullptr;     // column-block kernel: stored rows per group
     int dstride = 0;
     int lds_rows = 0;               // column-block kernel: stored rows kept in LDS
+    int ring_rows = 0;              // column-block kernel: slots of the stored-row ring (0: 64 rows)
     bool cols = false;              // column-block kernel selected
     bool wide = false;              // windows of 65..128 characters (wide_kernel)
     // launch shape
@@ -119,7 +120,7 @@ int check_params(const scg_params* p) {
     // windows wider than 64: plain mode in the column-block form only, no yields or ablations
     if (p->W > 64 && (p->mode != SCG_MODE_PLAIN || p->kernel == SCG_KERNEL_ROWS || p->yield_chars > 0 ||
                       (p->flags & (SCG_FLAG_NO_EARLY_TERMINATION | SCG_FLAG_STORE_ALL_COLUMNS | SCG_FLAG_ROWS_LDS |
-                                   SCG_FLAG_STORE_EDGES))))
+                                   SCG_FLAG_STORE_EDGES | SCG_FLAG_ROW_RING))))
         return SCG_EINVAL;
     if (p->mode < SCG_MODE_PLAIN || p->mode > SCG_MODE_FIXED) return SCG_EINVAL;
     // column blocks without a learned budget also run 32 windows per wavefront
@@ -131,10 +132,16 @@ int check_params(const scg_params* p) {
     if (p->mode == SCG_MODE_LEARNED && !(p->tau > 0.f && p->tau <= 1.f)) return SCG_EINVAL;
     if (p->yield_chars > 0 && p->yield_chars < p->W - p->O) return SCG_EINVAL;
     if (p->kernel < SCG_KERNEL_AUTO || p->kernel > SCG_KERNEL_COLUMNS) return SCG_EINVAL;
-    constexpr int32_t kAblations =
-        SCG_FLAG_NO_EARLY_TERMINATION | SCG_FLAG_STORE_ALL_COLUMNS | SCG_FLAG_ROWS_LDS | SCG_FLAG_STORE_EDGES;
+    constexpr int32_t kAblations = SCG_FLAG_NO_EARLY_TERMINATION | SCG_FLAG_STORE_ALL_COLUMNS | SCG_FLAG_ROWS_LDS |
+                                   SCG_FLAG_STORE_EDGES | SCG_FLAG_ROW_RING;
     if (p->flags & ~(SCG_FLAG_GRAPH | kAblations)) return SCG_EINVAL;
     if ((p->flags & kAblations) && (p->mode != SCG_MODE_PLAIN || p->kernel == SCG_KERNEL_ROWS)) return SCG_EINVAL;
+    // the row ring keeps only the rows ending at d_w: it needs early termination and the
+    // global region; 4, 8 or 16 windows per wavefront
+    if ((p->flags & SCG_FLAG_ROW_RING) &&
+        ((p->flags & (SCG_FLAG_NO_EARLY_TERMINATION | SCG_FLAG_ROWS_LDS)) || (p->slots > 8 && p->slots <= 10) ||
+         p->slots > 16))
+        return SCG_EINVAL;
     // edges are stored as whole 64-bit words, in global memory, with 4, 8 or 16 windows per wavefront
     if ((p->flags & SCG_FLAG_STORE_EDGES) && ((p->flags & SCG_FLAG_ROWS_LDS) || (p->slots > 16 && p->slots != 0) ||
                                                (p->slots > 8 && p->slots <= 10)))
@@ -233,6 +240,7 @@ int enqueue_run(scg_batch* b, hipStream_t s, int32_t* edits, int32_t* text_end, 
     a.dstride = b->dstride;
     a.lds_rows = b->lds_rows;
     a.edges = (b->p.flags & SCG_FLAG_STORE_EDGES) ? 1 : 0;
+    a.ring_rows = b->ring_rows;
     a.no_et = (b->p.flags & SCG_FLAG_NO_EARLY_TERMINATION) ? 1 : 0;
     if (b->npairs > 0) {
         if (b->wide) HIP_TRY(launch_align_wide(a, b->grid, b->ns, s));
@@ -586,10 +594,17 @@ int scg_batch_create(scg_ctx* c, const scg_params* params, int32_t npairs, const
         const bool lr = (params->flags & SCG_FLAG_ROWS_LDS) && (b->ns == 4 || b->ns == 8 || b->ns == 16);
         b->lds_rows = 0;
         b->lds = 0;
+        // extended DENT: traceback reads at most W-O rows below d_w, and the lanes ahead
+        // of column 0 store at most 64/ns rows above it before early termination
+        b->ring_rows = 0;
+        if (params->flags & SCG_FLAG_ROW_RING) {
+            const int ring = cap + 64 / b->ns + 1;
+            if (ring < 64) b->ring_rows = ring;
+        }
         if (lr) {
             const int scap = (params->flags & SCG_FLAG_STORE_ALL_COLUMNS) ? 63 : cap;
             const size_t rowb = (size_t)b->ns * cols_lds_row_bytes(learned, cap, cols_dent_stride(scap, b->ns));
-            int vg = cols_max_blocks_per_cu(learned, b->ns, 0, cap, true, false);
+            int vg = cols_max_blocks_per_cu(learned, b->ns, 0, cap, 1, false);
             if (params->waves_per_cu > 0) vg = std::min(vg, params->waves_per_cu);
             const int64_t waves = (npairs + b->ns - 1) / b->ns;
             const int resident = (int)std::max<int64_t>(1, std::min<int64_t>(vg, (waves + c->num_cu - 1) / c->num_cu));
@@ -599,7 +614,8 @@ int scg_batch_create(scg_ctx* c, const scg_params* params, int32_t npairs, const
             b->lds_rows = std::min(rows, 64);
             b->lds = (size_t)b->lds_rows * rowb;
         }
-        per_cu = cols_max_blocks_per_cu(learned, b->ns, b->lds, cap, b->lds_rows > 0, edges);
+        per_cu = cols_max_blocks_per_cu(learned, b->ns, b->lds, cap, b->lds_rows > 0 ? 1 : (b->ring_rows > 0 ? 2 : 0),
+                                        edges);
     } else {
         b->ns = params->slots > 0 ? params->slots : (params->mode == SCG_MODE_PLAIN ? 1 : 4);
         b->lds = align_lds_bytes(params->W - params->O + 1, b->ns);
@@ -620,7 +636,8 @@ int scg_batch_create(scg_ctx* c, const scg_params* params, int32_t npairs, const
         const int scap = (params->flags & SCG_FLAG_STORE_ALL_COLUMNS) ? 63 : cap;
         b->dstride = cols_dent_stride(scap, b->ns);
         const bool edges = (params->flags & SCG_FLAG_STORE_EDGES) != 0;
-        if ((rc = dev_alloc(&b->dent_d, cols_dent_bytes(b->grid, scap, b->ns, edges) / sizeof(uint64_t)))) return fail(rc);
+        if ((rc = dev_alloc(&b->dent_d, cols_dent_bytes(b->grid, scap, b->ns, edges, b->ring_rows) / sizeof(uint64_t))))
+            return fail(rc);
     }
     *out = b;
     return SCG_OK;

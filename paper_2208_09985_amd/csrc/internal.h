@@ -77,6 +77,7 @@ struct AlignArgs {
     int32_t dstride;
     int32_t lds_rows;             // rows 0..lds_rows-1 of each group's stored region are in LDS
     int32_t edges;                // ablation: stored slots hold edge bitvectors, not entries
+    int32_t ring_rows;            // > 0: stored rows kept as a ring of this many slots (extended DENT)
     int32_t no_et;                // ablation: rows continue past d_w up to k_w
 };
 
@@ -91,8 +92,8 @@ int align_max_blocks_per_cu(size_t lds_bytes, bool learned);
 hipError_t launch_align_cols(const AlignArgs& a, int grid, int ng, size_t lds, hipStream_t s);
 int cols_dent_stride(int cap, int ng);
 size_t cols_lds_row_bytes(bool learned, int cap, int stride);
-size_t cols_dent_bytes(int grid, int cap, int ng, bool edges);
-int cols_max_blocks_per_cu(bool learned, int ng, size_t lds, int cap, bool lds_rows, bool edges);
+size_t cols_dent_bytes(int grid, int cap, int ng, bool edges, int ring_rows);
+int cols_max_blocks_per_cu(bool learned, int ng, size_t lds, int cap, int sm, bool edges);
 hipError_t launch_align_wide(const AlignArgs& a, int grid, int ng, hipStream_t s);
 int wide_dent_stride(int cap, int ng);
 size_t wide_dent_bytes(int grid, int cap, int ng);

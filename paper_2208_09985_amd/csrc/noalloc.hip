@@ -197,10 +197,10 @@ extern "C" int scg_align_batch_noalloc(scg_ctx* c, const scg_params* params, int
                           : params->slots <= 16 ? 16 : 32)
                        : (npairs >= 8 * num_cu ? 8 : 4);
     const int cap = params->W - params->O;
-    int grid = cols_max_blocks_per_cu(false, ns, 0, cap, false, false) * num_cu;
+    int grid = cols_max_blocks_per_cu(false, ns, 0, cap, 0, false) * num_cu;
     if (params->waves_per_cu > 0) grid = std::min(grid, params->waves_per_cu * num_cu);
     grid = std::min<int64_t>(grid, (npairs + ns - 1) / ns);
-    const size_t per_wave = cols_dent_bytes(1, cap, ns, false);
+    const size_t per_wave = cols_dent_bytes(1, cap, ns, false, 0);
     grid = (int)std::min<size_t>((size_t)grid, kDentBytes / per_wave);
     if (grid < 1) return SCG_ELIMIT;
 
@@ -256,6 +256,7 @@ extern "C" int scg_align_batch_noalloc(scg_ctx* c, const scg_params* params, int
     a.dstride = cols_dent_stride(cap, ns);
     a.lds_rows = 0;   // every stored row in the workspace's global region
     a.edges = 0;
+    a.ring_rows = 0;
     a.no_et = 0;
     if ((e = launch_align_cols(a, grid, ns, 0, s)) != hipSuccess) return capi_from_hip(e, "align (column blocks)");
     return SCG_OK;

@@ -99,6 +99,7 @@ def test_window_parameters(ctx, W, O, k):
     check(ctx, b, W=W, O=O, k=k, mode="fixed", fixed_rows=3, what=f"W{W}O{O}k{k} fixed3")
     check(ctx, b, W=W, O=O, k=k, what=f"W{W}O{O}k{k} 10 windows per wavefront", kernels=("columns",), slots=10)
     check(ctx, b, W=W, O=O, k=k, what=f"W{W}O{O}k{k} edges stored", kernels=("columns",), store_edges=True)
+    check(ctx, b, W=W, O=O, k=k, what=f"W{W}O{O}k{k} row ring", kernels=("columns",), row_ring=True)
 
 
 def test_edge_cases(ctx):
@@ -111,6 +112,7 @@ def test_edge_cases(ctx):
     check(ctx, b, k=5, what="edge cases k=5 (not aligned)")
     check(ctx, b, what="edge cases, edges stored", kernels=("columns",), store_edges=True)
     check(ctx, b, what="edge cases, rows in LDS", kernels=("columns",), rows_lds=True)
+    check(ctx, b, what="edge cases, row ring", kernels=("columns",), row_ring=True)
 
 
 def test_bad_device_input_marks_pair(ctx):
@@ -159,7 +161,8 @@ def test_ablation_flags_keep_results(ctx, W, O):
                dict(rows_lds=True, store_all_columns=True, slots=16), dict(rows_lds=True, slots=4, waves_per_cu=1),
                dict(rows_lds=True, no_early_termination=True), dict(store_edges=True),
                dict(store_edges=True, no_early_termination=True, store_all_columns=True, slots=4),
-               dict(store_edges=True, slots=16)):
+               dict(store_edges=True, slots=16), dict(row_ring=True), dict(row_ring=True, slots=4),
+               dict(row_ring=True, slots=16, store_edges=True, store_all_columns=True)):
         log(f"[parity] ablation W={W} O={O} {kw}")
         compare(b, run_gpu(ctx, b, W=W, O=O, k=W, kernel="columns", **kw), ref, f"ablation {kw}")
 
@@ -210,6 +213,10 @@ def test_unrelated_pairs_long_tracebacks(ctx):
         check(ctx, b, what=f"unrelated slots={slots}", kernels=("columns",), slots=slots)
     check(ctx, b, what="unrelated, edges stored", kernels=("columns",), store_edges=True)
     check(ctx, b, what="unrelated, rows in LDS", kernels=("columns",), rows_lds=True)
+    # distances above W-O: the row ring wraps within a window
+    for slots in (4, 8, 16):
+        check(ctx, b, what=f"unrelated, row ring slots={slots}", kernels=("columns",), row_ring=True, slots=slots)
+    check(ctx, b, W=64, O=40, k=64, what="unrelated, row ring W64 O40", kernels=("columns",), row_ring=True)
     check(ctx, b, what="unrelated rows", kernels=("rows",))
 
 
