@@ -111,8 +111,11 @@ enum {
 enum {
     SCG_KERNEL_AUTO = 0,     /* column blocks in plain mode, error rows with a row budget     */
     SCG_KERNEL_ROWS = 1,     /* lanes are error rows; windows packed as lane segments          */
-    SCG_KERNEL_COLUMNS = 2   /* 4/8/16 windows per wavefront (32 without a learned budget),   */
+    SCG_KERNEL_COLUMNS = 2,  /* 4/8/16 windows per wavefront (32 without a learned budget),   */
                              /* lanes own text columns; a pass of row steps, then tracebacks   */
+    SCG_KERNEL_LANES = 3     /* one lane per pair, rows computed in order over all columns,  */
+                             /* the latest W-O+1 rows kept (the paper's row-wise CPU mapping; */
+                             /* plain mode, W <= 64, no yields or ablation flags)             */
 };
 
 typedef struct {

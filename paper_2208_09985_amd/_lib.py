@@ -24,7 +24,7 @@ FLAG_STORE_ALL_COLUMNS = 4
 FLAG_ROWS_LDS = 8
 FLAG_STORE_EDGES = 16
 FLAG_ROW_RING = 32
-KERNEL_AUTO, KERNEL_ROWS, KERNEL_COLUMNS = 0, 1, 2
+KERNEL_AUTO, KERNEL_ROWS, KERNEL_COLUMNS, KERNEL_LANES = 0, 1, 2, 3
 NFEATURES = 16
 
 EXPORTED = [

@@ -50,7 +50,8 @@ def params(W=64, O=24, k=64, mode="plain", slots=0, waves_per_cu=0, order="input
                | (L.FLAG_STORE_EDGES if store_edges else 0) | (L.FLAG_ROW_RING if row_ring else 0))
     if yield_chars is not None:
         p.yield_chars = yield_chars
-    p.kernel = {"auto": L.KERNEL_AUTO, "rows": L.KERNEL_ROWS, "columns": L.KERNEL_COLUMNS}[kernel]
+    p.kernel = {"auto": L.KERNEL_AUTO, "rows": L.KERNEL_ROWS, "columns": L.KERNEL_COLUMNS,
+                "lanes": L.KERNEL_LANES}[kernel]
     return p
 
 

@@ -17,7 +17,7 @@ import tempfile
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libscrooge_hip.so")
-SOURCES = ["pack.hip", "align.hip", "align_cols.hip", "align_wide.hip", "mlp.hip", "io.hip", "noalloc.hip", "capi.cpp"]
+SOURCES = ["pack.hip", "align.hip", "align_cols.hip", "align_wide.hip", "align_lane.hip", "mlp.hip", "io.hip", "noalloc.hip", "capi.cpp"]
 # the resource microbenchmarks (VALU, LDS, load latency) are a library of their own
 PEAK_LIB = os.path.join(HERE, "libscrooge_peak.so")
 PEAK_SOURCES = ["peak.hip"]

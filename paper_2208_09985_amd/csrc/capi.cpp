@@ -67,6 +67,7 @@ struct scg_batch {
     int ring_rows = 0;              // column-block kernel: slots of the stored-row ring (0: 64 rows)
     bool cols = false;              // column-block kernel selected
     bool wide = false;              // windows of 65..128 characters (wide_kernel)
+    bool lanes = false;             // one lane per pair, rows computed in order (lane_kernel)
     // launch shape
     int ns = 1;
     int grid = 1;
@@ -131,7 +132,11 @@ int check_params(const scg_params* p) {
     if (p->mode == SCG_MODE_FIXED && (p->fixed_rows < 1 || p->fixed_rows > 64)) return SCG_EINVAL;
     if (p->mode == SCG_MODE_LEARNED && !(p->tau > 0.f && p->tau <= 1.f)) return SCG_EINVAL;
     if (p->yield_chars > 0 && p->yield_chars < p->W - p->O) return SCG_EINVAL;
-    if (p->kernel < SCG_KERNEL_AUTO || p->kernel > SCG_KERNEL_COLUMNS) return SCG_EINVAL;
+    if (p->kernel < SCG_KERNEL_AUTO || p->kernel > SCG_KERNEL_LANES) return SCG_EINVAL;
+    // one lane per pair: plain mode, W <= 64, no yields or flags besides the graph
+    if (p->kernel == SCG_KERNEL_LANES &&
+        (p->mode != SCG_MODE_PLAIN || p->W > 64 || p->yield_chars > 0 || (p->flags & ~SCG_FLAG_GRAPH)))
+        return SCG_EINVAL;
     constexpr int32_t kAblations = SCG_FLAG_NO_EARLY_TERMINATION | SCG_FLAG_STORE_ALL_COLUMNS | SCG_FLAG_ROWS_LDS |
                                    SCG_FLAG_STORE_EDGES | SCG_FLAG_ROW_RING;
     if (p->flags & ~(SCG_FLAG_GRAPH | kAblations)) return SCG_EINVAL;
@@ -243,7 +248,8 @@ int enqueue_run(scg_batch* b, hipStream_t s, int32_t* edits, int32_t* text_end, 
     a.ring_rows = b->ring_rows;
     a.no_et = (b->p.flags & SCG_FLAG_NO_EARLY_TERMINATION) ? 1 : 0;
     if (b->npairs > 0) {
-        if (b->wide) HIP_TRY(launch_align_wide(a, b->grid, b->ns, s));
+        if (b->lanes) HIP_TRY(launch_align_lane(a, b->grid, s));
+        else if (b->wide) HIP_TRY(launch_align_wide(a, b->grid, b->ns, s));
         else if (b->cols) HIP_TRY(launch_align_cols(a, b->grid, b->ns, b->lds, s));
         else HIP_TRY(launch_align(a, b->grid, b->lds, s));
     }
@@ -494,7 +500,11 @@ int scg_batch_create(scg_ctx* c, const scg_params* params, int32_t npairs, const
     // advance every pair by one window, so pairs finish together anyway)
     b->wide = params->W > 64;
     if (b->wide) b->cols = false;
-    if (b->p.yield_chars < 0) b->p.yield_chars = (b->cols || b->wide) ? 0 : 1280;
+    b->lanes = params->kernel == SCG_KERNEL_LANES;
+    if (b->lanes) b->cols = false;
+    // the row-lane kernel is the only one that yields by default; the one-lane
+    // kernel never yields (its queue holds exactly the pairs)
+    if (b->p.yield_chars < 0) b->p.yield_chars = (b->cols || b->wide || b->lanes) ? 0 : 1280;
     // windows wider than 64 read three planes words from their start: two padding words
     const int pad_words = b->wide ? 2 : 1;
     // host-side tables
@@ -568,7 +578,11 @@ int scg_batch_create(scg_ctx* c, const scg_params* params, int32_t npairs, const
     // launch shape
     const bool learned = params->mode == SCG_MODE_LEARNED;
     int per_cu;
-    if (b->wide) {
+    if (b->lanes) {
+        b->ns = 64;   // a pair per lane
+        b->lds = 0;
+        per_cu = lane_max_blocks_per_cu();
+    } else if (b->wide) {
         // 4 or 8 windows per wavefront (16 or 8 lanes of 8 or 16 columns each);
         // automatic: 8 with whole 128-bit entries (W - O > 95) once that still
         // gives every SIMD a wavefront, else 4 (with 8- or 12-byte entries the
@@ -625,6 +639,10 @@ int scg_batch_create(scg_ctx* c, const scg_params* params, int32_t npairs, const
     b->grid = std::max(1, per_cu * c->num_cu);
     const int64_t need = (npairs + b->ns - 1) / b->ns;   // more wavefronts than slots-worth of pairs idle
     if (b->grid > need) b->grid = (int)std::max<int64_t>(1, need);
+    if (b->lanes && npairs > 0) {
+        if ((rc = dev_alloc(&b->dent_d, lane_dent_bytes(b->grid, params->W - params->O) / sizeof(uint64_t))))
+            return fail(rc);
+    }
     if (b->wide && npairs > 0) {
         const int cap = params->W - params->O;
         b->dstride = wide_dent_stride(cap, b->ns);

@@ -114,6 +114,9 @@ hipError_t launch_repack2(const uint64_t* in, const int64_t* inword, const int32
 hipError_t launch_runs_to_ops(const uint32_t* runs, const int64_t* runs_off, const int32_t* n_runs, int32_t npairs,
                               int32_t* rend, uint8_t* ops, const int64_t* ops_off, int32_t* n_ops, int num_cu,
                               hipStream_t s);
+size_t lane_dent_bytes(int grid, int cap);
+int lane_max_blocks_per_cu();
+hipError_t launch_align_lane(const AlignArgs& a, int grid, hipStream_t s);
 int noalloc_init(int device);   // noalloc.hip: device address of its static workspace
 hipError_t launch_adam(int32_t n, float* p, const float* g, float* m, float* v, __half* p16, float lr,
                        float b1, float b2, float eps, int32_t step, hipStream_t s);

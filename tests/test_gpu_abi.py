@@ -133,3 +133,48 @@ def test_packed_input_prepared_batch(ctx, host):
         torch.cuda.synchronize()
         compare(b, bt.result(), ref, f"packed host={host} [{kern} {mode}]")
         bt.close()
+
+
+@pytest.mark.parametrize("kw", [dict(), dict(kernel="rows"), dict(kernel="lanes"), dict(kernel="columns", slots=10),
+                                dict(kernel="columns", slots=32), dict(kernel="columns", row_ring=True),
+                                dict(kernel="columns", rows_lds=True), dict(kernel="columns", store_edges=True),
+                                dict(W=128, O=24, k=128), dict(mode="fixed", fixed_rows=7)])
+def test_outputs_stay_inside_their_buffers(ctx, kw):
+    """Every kernel writes the caller's output arrays only inside them: guard
+    elements around edits, text_end, status, n_ops and the run words keep their
+    sentinel value (pairs of several lengths, empty and bad ones included)."""
+    import torch
+    from paper_2208_09985_amd import api, _lib as L
+    b = synth.make_batch("mixed_10kbp", 70)
+    pats = [b.pattern(i)[:int(300 + 37 * i)] for i in range(b.npairs)] + [b"", b"ACGT", b"ACNT"]
+    txts = [b.text(i)[:int(310 + 29 * i)] for i in range(b.npairs)] + [b"AC", b"", b"ACGT"]
+    b = synth.from_lists(pats, txts)
+    n = b.npairs
+    G, S = 64, -12345
+    dev = torch.device("cuda:0")
+    prm = api.params(**kw)
+    pat = torch.from_numpy(b.pat).to(dev)
+    txt = torch.from_numpy(b.txt).to(dev)
+    po, to = np.ascontiguousarray(b.pat_off), np.ascontiguousarray(b.txt_off)
+    h = ctypes.c_void_p()
+    P = lambda t: ctypes.c_void_p(t.data_ptr())
+    lib = ctx._lib
+    torch.cuda.synchronize()
+    L.check(lib.scg_batch_create(ctx.handle, ctypes.byref(prm), n, P(pat), ctypes.c_void_p(po.ctypes.data),
+                                 P(txt), ctypes.c_void_p(to.ctypes.data), L.INPUT_ASCII, L.WHERE_DEVICE, None,
+                                 ctypes.byref(h)), "scg_batch_create")
+    cap = int(lib.scg_batch_runs_capacity(h))
+    outs = [torch.full((n + 2 * G,), S, dtype=torch.int32, device=dev) for _ in range(4)]
+    runs = torch.full((cap + 2 * G,), S, dtype=torch.int32, device=dev)
+    inner = lambda t: ctypes.c_void_p(t.data_ptr() + 4 * G)
+    log(f"[abi] guarded outputs {kw}")
+    for _ in range(2):
+        L.check(lib.scg_batch_run(h, None, inner(outs[0]), inner(outs[1]), inner(outs[2]), inner(runs),
+                                  inner(outs[3])), "scg_batch_run")
+    torch.cuda.synchronize()
+    lib.scg_batch_destroy(h)
+    for t in outs + [runs]:
+        v = t.cpu().numpy()
+        assert np.all(v[:G] == S) and np.all(v[-G:] == S), kw
+    st = outs[2].cpu().numpy()[G:G + n]
+    assert list(st[-3:]) == [0, 0, L.PAIR_BAD_INPUT]

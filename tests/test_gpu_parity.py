@@ -39,7 +39,7 @@ def check(ctx, batch, W=64, O=24, k=64, what="", kernels=KERNELS, **kw):
 def test_small_100bp_all_pairs_plain(ctx):
     b = synth.make_batch("small_100bp")
     ref = oracle.align_batch(b, 64, 24, 64)
-    for kern in KERNELS:
+    for kern in KERNELS + ("lanes",):
         gpu, _ = check(ctx, b, what="small_100bp plain", kernels=(kern,))
         assert gpu.stats.windows == ref["stats"].windows
         assert gpu.stats.ops_alg == ref["stats"].ops_alg
@@ -65,7 +65,7 @@ def test_short_250bp_subset(ctx):
 
 def test_long_10kbp_sample(ctx):
     b = synth.make_batch("long_10kbp", 48)
-    check(ctx, b, what="long_10kbp")
+    check(ctx, b, what="long_10kbp", kernels=KERNELS + ("lanes",))
     check(ctx, b, mode="fixed", fixed_rows=16, what="long_10kbp fixed16")
 
 
@@ -100,6 +100,7 @@ def test_window_parameters(ctx, W, O, k):
     check(ctx, b, W=W, O=O, k=k, what=f"W{W}O{O}k{k} 10 windows per wavefront", kernels=("columns",), slots=10)
     check(ctx, b, W=W, O=O, k=k, what=f"W{W}O{O}k{k} edges stored", kernels=("columns",), store_edges=True)
     check(ctx, b, W=W, O=O, k=k, what=f"W{W}O{O}k{k} row ring", kernels=("columns",), row_ring=True)
+    check(ctx, b, W=W, O=O, k=k, what=f"W{W}O{O}k{k} one lane per pair", kernels=("lanes",))
 
 
 def test_edge_cases(ctx):
@@ -113,6 +114,8 @@ def test_edge_cases(ctx):
     check(ctx, b, what="edge cases, edges stored", kernels=("columns",), store_edges=True)
     check(ctx, b, what="edge cases, rows in LDS", kernels=("columns",), rows_lds=True)
     check(ctx, b, what="edge cases, row ring", kernels=("columns",), row_ring=True)
+    check(ctx, b, what="edge cases, one lane per pair", kernels=("lanes",))
+    check(ctx, b, k=5, what="edge cases k=5, one lane per pair", kernels=("lanes",))
 
 
 def test_bad_device_input_marks_pair(ctx):
@@ -217,6 +220,8 @@ def test_unrelated_pairs_long_tracebacks(ctx):
     for slots in (4, 8, 16):
         check(ctx, b, what=f"unrelated, row ring slots={slots}", kernels=("columns",), row_ring=True, slots=slots)
     check(ctx, b, W=64, O=40, k=64, what="unrelated, row ring W64 O40", kernels=("columns",), row_ring=True)
+    check(ctx, b, what="unrelated, one lane per pair", kernels=("lanes",))
+    check(ctx, b, W=64, O=40, k=64, what="unrelated, one lane per pair W64 O40", kernels=("lanes",))
     check(ctx, b, what="unrelated rows", kernels=("rows",))
 
 
@@ -242,6 +247,7 @@ def test_long_one_sided_indels(ctx):
     check(ctx, b, what="long indels")
     for slots in (4, 10, 16):
         check(ctx, b, what=f"long indels slots={slots}", kernels=("columns",), slots=slots)
+    check(ctx, b, what="long indels, one lane per pair", kernels=("lanes",))
 
 
 def test_one_shot_batch_call(ctx):

@@ -76,6 +76,9 @@ def test_long_10kbp_all_pairs_plain_and_learned(ctx):
     for slots in (10, 16):
         log(f"[full] long_10kbp plain, {slots} windows per wavefront")
         compare(b, api.align_batch(ctx, b, kernel="columns", slots=slots), ref, f"long_10kbp full slots={slots}")
+    for kw in (dict(rows_lds=True), dict(row_ring=True), dict(kernel="lanes")):
+        log(f"[full] long_10kbp plain, {kw}")
+        compare(b, api.align_batch(ctx, b, **{"kernel": "columns", **kw}), ref, f"long_10kbp full {kw}")
     log("[full] long_10kbp learned (committed predictor), default kernel")
     compare(b, api.align_batch(ctx, b, mode="learned"), ref, "long_10kbp full learned")
 
@@ -95,6 +98,15 @@ def test_uneven_lognormal_all_pairs_autotuned_graph(ctx):
         compare(b, gb.result(), ref, f"uneven_lognormal full graph replay {rep} {best}")
         _ = torch.ones(1000, device=gb.dev).sum().item()   # eager work between replays
     gb.close()
+
+
+def test_mixed_10kbp_all_pairs_one_lane_per_pair(ctx):
+    from paper_2208_09985_amd import api
+    w, b, ref = _workload("mixed_10kbp")
+    log("[full] mixed_10kbp plain, one lane per pair")
+    res = api.align_batch(ctx, b, W=w.W, O=w.O, k=w.k, kernel="lanes")
+    compare(b, res, ref, "mixed_10kbp full lanes")
+    assert res.stats.yields == 0
 
 
 @pytest.mark.parametrize("kernel", ["auto", "columns"])
