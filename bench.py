@@ -322,6 +322,16 @@ def main():
             e = summary(batch, lms_, lst_)
             e["lanes_per_window"] = 64 // ng
             lanes[f"windows_per_wavefront_{ng}"] = e
+        # the other end of the mapping: one lane per pair, rows in order (the paper's CPU mapping),
+        # and the column-block kernel with its stored rows as a ring (DENT extended to rows) or with
+        # the lowest rows in LDS
+        for tag, kw in (("one_lane_per_pair_rowwise", dict(kernel="lanes")),
+                        ("columns_row_ring", dict(kernel="columns", row_ring=True)),
+                        ("columns_rows_in_lds", dict(kernel="columns", rows_lds=True))):
+            xms, xst, xres = measure(batch, f"mapping {tag}", api.params(W=w.W, O=w.O, k=w.k, mode="plain", **kw), 3, 1)
+            e = summary(batch, xms, xst, same_output(xres, res))
+            e["frac"] = round(xst.ops_alg / (xst.kernel_ms_avg / 1e3) / 1e12 / PEAK_T64OPS, 5)
+            lanes[tag] = e
         workloads["column_blocks_long_10kbp"] = lanes
         # the paper's three improvements (SENE: entries, not edges; DENT: only the columns traceback
         # reads; ET: rows stop at d_w) switched off in every combination, with the stored rows in global

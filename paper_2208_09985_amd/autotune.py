@@ -37,7 +37,7 @@ SPACE = {
               "rows_lds": [False, True]},
     "fixed": {"kernel": ["rows"], "slots": [2, 4, 6, 8], "waves_per_cu": [0], "order": ["input"],
               "fixed_rows": [7, 11, 15, 23]},
-    "learned": {"kernel": ["rows"], "slots": [2, 4, 6], "waves_per_cu": [0], "order": ["input"],
+    "learned": {"kernel": ["rows", "columns"], "slots": [4, 8], "waves_per_cu": [0], "order": ["input"],
                 "tau": [0.7, 0.8, 0.9]},
 }
 
