@@ -206,9 +206,12 @@ def main():
     if have_model:
         ctx.load_model(WEIGHTS)
 
+    shapes = {}
+
     def measure(batch, name, prm, steps, warmup):
         log(f"[bench] {name}: prepare")
         b = api.Batch(ctx, batch, prm)
+        shapes[name] = b.launch_shape()
         ms, st = timed_steps(b, steps, warmup)
         res = b.result()
         ok = bool(np.all(res.status == 0))
@@ -371,6 +374,10 @@ def main():
         workloads["more_pairs_long_10kbp"] = scale
 
     achieved = st.ops_alg / (st.kernel_ms_avg / 1e3) / 1e12
+    shape = shapes["plain"]
+    kname = (f"cols_kernel<false, {shape['slots']}, {stored_form(w.W - w.O)}, 0"
+             + (", true>" if shape["one_per_simd"] else ">"))
+    lanes_per_window = 64 // shape["slots"] if shape["slots"] != 10 else 6
     out = {
         "metric": METRIC,
         "value": round(batch.npairs / (ms / 1e3), 1),
@@ -393,8 +400,14 @@ def main():
                      "peak_sclk_mhz": round(PEAK_SCLK, 1) if PEAK_SCLK else None,
                      "peak_nominal": round(PEAK_NOMINAL, 3),
                      "traffic": measured_traffic("cols_kernel_plain"),
-                     "kernel": f"cols_kernel<false, 8, {stored_form(w.W - w.O)}>", "kernel_ms": round(st.kernel_ms_avg, 4),
-                     "ops_alg_per_launch": int(st.ops_alg), "windows_per_launch": int(st.windows)},
+                     "kernel": kname, "kernel_ms": round(st.kernel_ms_avg, 4),
+                     "launch": shape,
+                     "ops_alg_per_launch": int(st.ops_alg), "windows_per_launch": int(st.windows),
+                     # lockstep: a pass of a wavefront runs as many row steps as its deepest
+                     # window needs; rows_needed is the mean of d_w + 1
+                     "lockstep": {"row_steps_per_window": round(st.lane_steps / 64 * shape["slots"] / max(st.windows, 1), 2),
+                                  "rows_needed_per_window": round(st.rows_budgeted / max(st.windows, 1), 2),
+                                  "skew_steps": lanes_per_window - 1}},
         "variants": variants,
         "workloads": workloads,
     }

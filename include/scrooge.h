@@ -135,6 +135,13 @@ typedef struct {
                             /* < 0: automatic, 1280 for error-row lanes, 0 for column  */
                             /* blocks)                                                 */
     int32_t kernel;         /* SCG_KERNEL_*                                            */
+    int32_t one_per_simd;   /* column blocks, plain mode, rows in global memory, 4, 8  */
+                            /* or 10 windows per wavefront: 1 = the form that holds a  */
+                            /* whole SIMD per wavefront (the grid is then at most one  */
+                            /* wavefront per SIMD); 0 = automatic, that form whenever  */
+                            /* the batch's wavefronts fit one per SIMD (10 windows per */
+                            /* wavefront are then picked when 8 would not fit); -1 =   */
+                            /* never.  Results are the same either way                 */
 } scg_params;
 
 typedef struct {
@@ -211,6 +218,15 @@ void scg_batch_destroy(scg_batch* b);
  * start offsets into it (npairs+1 int64, host memory). */
 int64_t scg_batch_runs_capacity(const scg_batch* b);
 int scg_batch_runs_offsets(const scg_batch* b, int64_t* out);
+
+/* The launch shape the batch was created with (a query; no device work).
+ * out[0] kernel: SCG_KERNEL_ROWS, SCG_KERNEL_COLUMNS, SCG_KERNEL_LANES, or 4
+ * for the wide-window column form (W > 64); out[1] windows per wavefront;
+ * out[2] wavefronts in the grid; out[3] dynamic LDS bytes per wavefront;
+ * out[4] 1 for the form holding a whole SIMD per wavefront; out[5] stored
+ * entry bits (32, 48 or 64; 96 or 128 for wide windows; 0 for error-row
+ * lanes).  out: 6 int32 in host memory.  Errors: SCG_EINVAL. */
+int scg_batch_launch_shape(const scg_batch* b, int32_t* out);
 
 /* Align the batch: encode+pack (Section 2.5's 2-bit encoding), then the
  * persistent fused DC+TB kernel.  All outputs are DEVICE pointers of npairs

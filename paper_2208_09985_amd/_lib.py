@@ -30,6 +30,7 @@ NFEATURES = 16
 EXPORTED = [
     "scg_strerror", "scg_last_hip_error", "scg_params_default", "scg_create", "scg_destroy", "scg_device_cus", "scg_set_model",
     "scg_batch_create", "scg_batch_destroy", "scg_batch_runs_capacity", "scg_batch_runs_offsets",
+    "scg_batch_launch_shape",
     "scg_batch_run", "scg_batch_stats", "scg_align", "scg_align_batch", "scg_last_stats", "scg_last_stats_all",
     "scg_runs_to_cigar", "scg_ops_to_cigar",
     "scg_features",
@@ -44,6 +45,7 @@ class Params(ctypes.Structure):
         ("mode", ctypes.c_int32), ("slots", ctypes.c_int32), ("waves_per_cu", ctypes.c_int32),
         ("order", ctypes.c_int32), ("fixed_rows", ctypes.c_int32), ("tau", ctypes.c_float),
         ("flags", ctypes.c_int32), ("yield_chars", ctypes.c_int32), ("kernel", ctypes.c_int32),
+        ("one_per_simd", ctypes.c_int32),
     ]
 
 
@@ -91,6 +93,7 @@ def load():
         "scg_batch_destroy": ([P], None),
         "scg_batch_runs_capacity": ([P], i64),
         "scg_batch_runs_offsets": ([P, P], ctypes.c_int),
+        "scg_batch_launch_shape": ([P, P], ctypes.c_int),
         "scg_batch_run": ([P, P, P, P, P, P, P], ctypes.c_int),
         "scg_batch_stats": ([P, ctypes.POINTER(Stats)], ctypes.c_int),
         "scg_align_batch": ([P, ctypes.POINTER(Params), i32, P, P, P, P, i32, i32, P, P, P, P, P, P, P], ctypes.c_int),

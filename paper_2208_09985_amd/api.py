@@ -34,7 +34,8 @@ def _stream_ptr(stream) -> ctypes.c_void_p:
 
 def params(W=64, O=24, k=64, mode="plain", slots=0, waves_per_cu=0, order="input", fixed_rows=None, tau=None,
            graph=False, yield_chars=None, kernel="auto", no_early_termination=False,
-           store_all_columns=False, rows_lds=False, store_edges=False, row_ring=False) -> L.Params:
+           store_all_columns=False, rows_lds=False, store_edges=False, row_ring=False,
+           one_per_simd="auto") -> L.Params:
     p = L.Params()
     L.load().scg_params_default(ctypes.byref(p))
     p.W, p.O, p.k = W, O, k
@@ -52,6 +53,7 @@ def params(W=64, O=24, k=64, mode="plain", slots=0, waves_per_cu=0, order="input
         p.yield_chars = yield_chars
     p.kernel = {"auto": L.KERNEL_AUTO, "rows": L.KERNEL_ROWS, "columns": L.KERNEL_COLUMNS,
                 "lanes": L.KERNEL_LANES}[kernel]
+    p.one_per_simd = {"auto": 0, True: 1, False: -1}[one_per_simd]
     return p
 
 
@@ -181,6 +183,13 @@ class Batch:
         rc = self._lib.scg_batch_run(self.handle, _stream_ptr(stream), _ptr(self.edits), _ptr(self.text_end),
                                      _ptr(self.status), _ptr(self.runs), _ptr(self.n_runs))
         L.check(rc, "scg_batch_run")
+
+    def launch_shape(self) -> dict:
+        out = (ctypes.c_int32 * 6)()
+        L.check(self._lib.scg_batch_launch_shape(self.handle, out), "scg_batch_launch_shape")
+        kernel = {L.KERNEL_ROWS: "rows", L.KERNEL_COLUMNS: "columns", L.KERNEL_LANES: "lanes", 4: "wide"}[out[0]]
+        return {"kernel": kernel, "slots": out[1], "grid": out[2], "lds_bytes": out[3], "one_per_simd": bool(out[4]),
+                "entry_bits": out[5]}
 
     def stats(self) -> L.Stats:
         st = L.Stats()

@@ -90,9 +90,17 @@ struct GroupRec {      // LDS: what the slot lane tells its group at set-up
 // lowest lds_rows rows in LDS, the others global.  2 (DENT extended to rows,
 // supplementary Section 1): a ring of ring_rows slots in the global region,
 // row d in slot d mod ring_rows.
-template <bool LEARNED, int NG, int ST, int SM>
+// OW: the wavefront reserves a whole SIMD.  Each pair's windows form a serial
+// chain, so the kernel's time is the time of its slowest wavefront, and a
+// wavefront that shares its SIMD with another runs its chain up to 1.5x
+// slower; the dispatcher does place two on one SIMD while others stay empty.
+// Claiming every accumulation register (this kernel issues no MFMA) makes a
+// wavefront's register block the whole of a SIMD's, so the hardware places at
+// most one per SIMD.  Used when the batch needs no more wavefronts than SIMDs.
+template <bool LEARNED, int NG, int ST, int SM, bool OW = false>
 __global__ __launch_bounds__(64) void cols_kernel(const AlignArgs a) {
     constexpr bool LR = SM == 1, RING = SM == 2;
+    if constexpr (OW) asm volatile("" ::: "a255");
     constexpr bool NARROW = ST == 1, SPLIT = ST == 2;
     // ST 3 (EDGES, the ablation of storing entries instead of edges): every
     // stored slot holds the three edge bitvectors of Algorithm 1 that the
@@ -492,25 +500,29 @@ __global__ __launch_bounds__(64) void cols_kernel(const AlignArgs a) {
                         const uint32_t c0 = (uint32_t)min(ti, stride - 1), c1 = (uint32_t)min(ti + 1, stride - 1);
                         const bool in_lds = rr < (uint32_t)R;
                         struct __attribute__((packed, aligned(4))) W2 { uint64_t v; };
-                        uint64_t llw = 0, lhw = 0, glw = 0, ghw = 0;
+                        uint64_t lw = 0, hw = 0;
                         // rows below R from LDS (every lane reads, at a clamped row); the
-                        // others from the global region, skipped when no lane needs one
+                        // others from the global region, skipped when no lane needs one.
+                        // The global words are consumed inside their branch, so an event
+                        // that reads only LDS waits for no vector-memory operation (the
+                        // counter it shares with the run-list stores)
                         if (R > 0) {
                             const uint32_t rl = min(rr, (uint32_t)R - 1u);
                             const uint32_t lo_row = lgbyte + rl * (SPLIT ? lobytes : rowbytes);
                             if (NARROW) {
-                                llw = *reinterpret_cast<const uint32_t*>(lrows + (lo_row + c0 * ESZ));
-                                lhw = *reinterpret_cast<const uint32_t*>(lrows + (lo_row + c1 * ESZ));
+                                lw = *reinterpret_cast<const uint32_t*>(lrows + (lo_row + c0 * ESZ));
+                                hw = *reinterpret_cast<const uint32_t*>(lrows + (lo_row + c1 * ESZ));
                             } else if (SPLIT) {
-                                llw = reinterpret_cast<const W2*>(lrows + (lo_row + c0 * 4u))->v;
-                                lhw = reinterpret_cast<const W2*>(lrows + (lhiplane + rl * hibytes + (c0 & ~1u) * 2u))->v;
+                                lw = reinterpret_cast<const W2*>(lrows + (lo_row + c0 * 4u))->v;
+                                hw = reinterpret_cast<const W2*>(lrows + (lhiplane + rl * hibytes + (c0 & ~1u) * 2u))->v;
                             } else {
-                                llw = *reinterpret_cast<const uint64_t*>(lrows + (lo_row + c0 * ESZ));
-                                lhw = *reinterpret_cast<const uint64_t*>(lrows + (lo_row + c1 * ESZ));
+                                lw = *reinterpret_cast<const uint64_t*>(lrows + (lo_row + c0 * ESZ));
+                                hw = *reinterpret_cast<const uint64_t*>(lrows + (lo_row + c1 * ESZ));
                             }
                         }
                         if (__ballot(!in_lds) != 0) {
                             const uint32_t lo_row = gbyte + __umul24(rr, SPLIT ? lobytes : rowbytes);
+                            uint64_t glw, ghw;
                             if (NARROW) {
                                 glw = *reinterpret_cast<const uint32_t*>(bdent + (lo_row + c0 * ESZ));
                                 ghw = *reinterpret_cast<const uint32_t*>(bdent + (lo_row + c1 * ESZ));
@@ -521,8 +533,9 @@ __global__ __launch_bounds__(64) void cols_kernel(const AlignArgs a) {
                                 glw = *reinterpret_cast<const uint64_t*>(bdent + (lo_row + c0 * ESZ));
                                 ghw = *reinterpret_cast<const uint64_t*>(bdent + (lo_row + c1 * ESZ));
                             }
+                            lw = in_lds ? lw : glw;
+                            hw = in_lds ? hw : ghw;
                         }
-                        const uint64_t lw = in_lds ? llw : glw, hw = in_lds ? lhw : ghw;
                         if (SPLIT) {
                             // columns ti and ti+1 of both planes, as one 8-byte word each (the
                             // 16-bit word from the 4-byte boundary at or below column ti)
@@ -719,6 +732,19 @@ static const void* cols_fn_plain(int ng, int sm) {
     return cols_fn<false, ST>(ng);
 }
 
+// the one-wavefront-per-SIMD forms: plain mode, rows in global memory, 4, 8 or
+// 10 windows per wavefront
+template <int ST>
+static const void* cols_fn_one(int ng) {
+    if (ng == 4) return (const void*)cols_kernel<false, 4, ST, 0, true>;
+    if (ng == 8) return (const void*)cols_kernel<false, 8, ST, 0, true>;
+    return (const void*)cols_kernel<false, 10, ST, 0, true>;
+}
+
+bool cols_one_per_simd_ok(bool learned, int ng, int sm, bool edges) {
+    return !learned && !edges && sm == 0 && (ng == 4 || ng == 8 || ng == 10);
+}
+
 // the edge-storing ablation form: plain mode, 4, 8 or 16 windows per wavefront
 static const void* cols_fn_edges(int ng, int sm) {
     if (sm == 2) {
@@ -731,10 +757,12 @@ static const void* cols_fn_edges(int ng, int sm) {
     return (const void*)cols_kernel<false, 16, 3, 0>;
 }
 
-int cols_max_blocks_per_cu(bool learned, int ng, size_t lds, int cap, int sm, bool edges) {
+int cols_max_blocks_per_cu(bool learned, int ng, size_t lds, int cap, int sm, bool edges, bool one) {
     int nb = 0;
     const int st = cols_store(learned, cap);
-    const void* f = learned ? cols_fn<true, 0>(ng)
+    if (one && !cols_one_per_simd_ok(learned, ng, sm, edges)) return 1;
+    const void* f = one ? (st == 1 ? cols_fn_one<1>(ng) : (st == 2 ? cols_fn_one<2>(ng) : cols_fn_one<0>(ng)))
+                  : learned ? cols_fn<true, 0>(ng)
                   : edges ? cols_fn_edges(ng, sm == 2 ? 2 : 0)
                   : (st == 1 ? cols_fn_plain<1>(ng, sm)
                              : (st == 2 ? cols_fn_plain<2>(ng, sm) : cols_fn_plain<0>(ng, sm)));
@@ -751,8 +779,15 @@ hipError_t launch_align_cols(const AlignArgs& a, int grid, int ng, size_t lds, h
     // launch below must use that layout, so a combination without one is refused
     if ((a.ring_rows > 0 || a.lds_rows > 0) && (learned || !small)) return hipErrorInvalidValue;
     if (a.edges && a.lds_rows > 0) return hipErrorInvalidValue;
+    if (a.one_per_simd && !cols_one_per_simd_ok(learned, ng, sm, a.edges != 0)) return hipErrorInvalidValue;
 #define SCG_COLS_LAUNCH(LRN, NGV, STV, LRV) \
     hipLaunchKernelGGL((cols_kernel<LRN, NGV, STV, LRV>), dim3(grid), dim3(64), lds, s, a)
+#define SCG_COLS_ONE(STV)                                                                          \
+    do {                                                                                           \
+        if (ng == 4) hipLaunchKernelGGL((cols_kernel<false, 4, STV, 0, true>), dim3(grid), dim3(64), lds, s, a);       \
+        else if (ng == 8) hipLaunchKernelGGL((cols_kernel<false, 8, STV, 0, true>), dim3(grid), dim3(64), lds, s, a);  \
+        else hipLaunchKernelGGL((cols_kernel<false, 10, STV, 0, true>), dim3(grid), dim3(64), lds, s, a);              \
+    } while (0)
 #define SCG_COLS_PLAIN(STV)                                  \
     do {                                                     \
         if (sm == 1) {                                       \
@@ -769,7 +804,11 @@ hipError_t launch_align_cols(const AlignArgs& a, int grid, int ng, size_t lds, h
         else if (ng == 10) SCG_COLS_LAUNCH(false, 10, STV, 0);       \
         else SCG_COLS_LAUNCH(false, 32, STV, 0);                     \
     } while (0)
-    if (a.edges) {
+    if (a.one_per_simd) {
+        if (st == 1) SCG_COLS_ONE(1);
+        else if (st == 2) SCG_COLS_ONE(2);
+        else SCG_COLS_ONE(0);
+    } else if (a.edges) {
         // the stored-row layout (64 rows or the ring) must be the one the host allocated
         if (sm == 2) {
             if (ng == 4) SCG_COLS_LAUNCH(false, 4, 3, 2);
@@ -790,6 +829,7 @@ hipError_t launch_align_cols(const AlignArgs& a, int grid, int ng, size_t lds, h
         SCG_COLS_PLAIN(0);
     }
 #undef SCG_COLS_PLAIN
+#undef SCG_COLS_ONE
 #undef SCG_COLS_LAUNCH
     return hipGetLastError();
 }

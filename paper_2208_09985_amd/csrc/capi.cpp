@@ -32,6 +32,7 @@ struct scg_ctx {
 
 struct scg_batch {
     scg_ctx* ctx = nullptr;
+    bool one = false;   // column blocks: one wavefront per SIMD
     scg_params p{};
     int32_t npairs = 0;
     // sequences (ASCII) on the device
@@ -151,6 +152,13 @@ int check_params(const scg_params* p) {
     if ((p->flags & SCG_FLAG_STORE_EDGES) && ((p->flags & SCG_FLAG_ROWS_LDS) || (p->slots > 16 && p->slots != 0) ||
                                                (p->slots > 8 && p->slots <= 10)))
         return SCG_EINVAL;
+    // a whole SIMD per wavefront: plain mode in the column-block kernel, rows in
+    // global memory, 4, 8 or 10 windows per wavefront
+    if (p->one_per_simd < -1 || p->one_per_simd > 1) return SCG_EINVAL;
+    if (p->one_per_simd == 1 &&
+        (p->mode != SCG_MODE_PLAIN || p->W > 64 || p->kernel == SCG_KERNEL_ROWS || p->kernel == SCG_KERNEL_LANES ||
+         (p->flags & (SCG_FLAG_ROWS_LDS | SCG_FLAG_STORE_EDGES | SCG_FLAG_ROW_RING)) || p->slots > 10))
+        return SCG_EINVAL;
     return SCG_OK;
 }
 
@@ -247,6 +255,7 @@ int enqueue_run(scg_batch* b, hipStream_t s, int32_t* edits, int32_t* text_end, 
     a.edges = (b->p.flags & SCG_FLAG_STORE_EDGES) ? 1 : 0;
     a.ring_rows = b->ring_rows;
     a.no_et = (b->p.flags & SCG_FLAG_NO_EARLY_TERMINATION) ? 1 : 0;
+    a.one_per_simd = b->one ? 1 : 0;
     if (b->npairs > 0) {
         if (b->lanes) HIP_TRY(launch_align_lane(a, b->grid, s));
         else if (b->wide) HIP_TRY(launch_align_wide(a, b->grid, b->ns, s));
@@ -594,12 +603,24 @@ int scg_batch_create(scg_ctx* c, const scg_params* params, int32_t npairs, const
     } else if (b->cols) {
         // windows per wavefront: 4, 8 or 16; automatic = enough wavefronts to
         // give every SIMD two of them
+        // Each pair's windows run one after another, so the kernel lasts as long as
+        // its slowest wavefront; one that shares a SIMD runs slower.  Automatic: 4
+        // windows per wavefront for small batches, 8 while the wavefronts fit one per
+        // SIMD, then 10 (six lanes of 12 columns) while those fit, else 8.
+        const int64_t simds = (int64_t)kSimdsPerCu * c->num_cu;
+        const bool plain_global = params->mode == SCG_MODE_PLAIN &&
+                                  !(params->flags & (SCG_FLAG_ROWS_LDS | SCG_FLAG_STORE_EDGES | SCG_FLAG_ROW_RING));
+        auto waves = [&](int ng) { return ((int64_t)npairs + ng - 1) / ng; };
         if (params->slots > 0)
             b->ns = params->slots <= 4 ? 4
                   : params->slots <= 8 ? 8
                   : (params->slots <= 10 && !learned) ? 10
                   : params->slots <= 16 ? 16 : 32;
-        else b->ns = npairs >= 8 * c->num_cu ? 8 : 4;
+        else if (npairs < 8 * c->num_cu) b->ns = 4;
+        else if (waves(8) > simds && waves(10) <= simds && plain_global && params->one_per_simd >= 0) b->ns = 10;
+        else b->ns = 8;
+        b->one = plain_global && (b->ns == 4 || b->ns == 8 || b->ns == 10) &&
+                 (params->one_per_simd == 1 || (params->one_per_simd == 0 && waves(b->ns) <= simds));
         // SCG_FLAG_ROWS_LDS: the lowest stored rows of each window in LDS, as
         // many as fit while every wavefront the batch needs (or the
         // register-limited maximum) stays resident on its CU
@@ -629,7 +650,7 @@ int scg_batch_create(scg_ctx* c, const scg_params* params, int32_t npairs, const
             b->lds = (size_t)b->lds_rows * rowb;
         }
         per_cu = cols_max_blocks_per_cu(learned, b->ns, b->lds, cap, b->lds_rows > 0 ? 1 : (b->ring_rows > 0 ? 2 : 0),
-                                        edges);
+                                        edges, b->one);
     } else {
         b->ns = params->slots > 0 ? params->slots : (params->mode == SCG_MODE_PLAIN ? 1 : 4);
         b->lds = align_lds_bytes(params->W - params->O + 1, b->ns);
@@ -667,6 +688,22 @@ void scg_batch_destroy(scg_batch* b) {
 }
 
 int64_t scg_batch_runs_capacity(const scg_batch* b) { return b ? b->runs_off_h.back() : -1; }
+
+int scg_batch_launch_shape(const scg_batch* b, int32_t* out) {
+    if (!b || !out) return SCG_EINVAL;
+    const int cap = b->p.W - b->p.O;
+    const bool learned = b->p.mode == SCG_MODE_LEARNED;
+    out[0] = b->wide ? 4 : (b->lanes ? SCG_KERNEL_LANES : (b->cols ? SCG_KERNEL_COLUMNS : SCG_KERNEL_ROWS));
+    out[1] = b->ns;
+    out[2] = b->grid;
+    out[3] = (int32_t)b->lds;
+    out[4] = b->one ? 1 : 0;
+    if (b->wide) out[5] = cap <= 95 ? 96 : 128;
+    else if (b->cols) out[5] = (b->p.flags & SCG_FLAG_STORE_EDGES) || learned ? 64 : (cap <= 31 ? 32 : (cap <= 47 ? 48 : 64));
+    else if (b->lanes) out[5] = 64;
+    else out[5] = 0;
+    return SCG_OK;
+}
 
 int scg_batch_runs_offsets(const scg_batch* b, int64_t* out) {
     if (!b || !out) return SCG_EINVAL;

@@ -27,6 +27,7 @@ enum {
 };
 
 constexpr int kMaxSlots = 16;     // windows in flight per wavefront
+constexpr int kSimdsPerCu = 4;    // SIMDs of a CDNA compute unit
 constexpr int kMaxClasses = 16;   // predictor classes
 constexpr int kMaxHidden = 64;
 constexpr int kFeatures = 16;
@@ -79,6 +80,7 @@ struct AlignArgs {
     int32_t edges;                // ablation: stored slots hold edge bitvectors, not entries
     int32_t ring_rows;            // > 0: stored rows kept as a ring of this many slots (extended DENT)
     int32_t no_et;                // ablation: rows continue past d_w up to k_w
+    int32_t one_per_simd;         // column blocks: the form that holds a whole SIMD per wavefront
 };
 
 // launchers (defined in the .hip files)
@@ -93,7 +95,8 @@ hipError_t launch_align_cols(const AlignArgs& a, int grid, int ng, size_t lds, h
 int cols_dent_stride(int cap, int ng);
 size_t cols_lds_row_bytes(bool learned, int cap, int stride);
 size_t cols_dent_bytes(int grid, int cap, int ng, bool edges, int ring_rows);
-int cols_max_blocks_per_cu(bool learned, int ng, size_t lds, int cap, int sm, bool edges);
+int cols_max_blocks_per_cu(bool learned, int ng, size_t lds, int cap, int sm, bool edges, bool one = false);
+bool cols_one_per_simd_ok(bool learned, int ng, int sm, bool edges);
 hipError_t launch_align_wide(const AlignArgs& a, int grid, int ng, hipStream_t s);
 int wide_dent_stride(int cap, int ng);
 size_t wide_dent_bytes(int grid, int cap, int ng);

@@ -154,6 +154,51 @@ def test_launch_shape_does_not_change_results(ctx):
         compare(b, run_gpu(ctx, b, mode="fixed", fixed_rows=12, **kw), ref, f"shape {kw}")
 
 
+@pytest.mark.parametrize("W,O", [(64, 24), (64, 33), (64, 10), (32, 17)])
+def test_one_wavefront_per_simd(ctx, W, O):
+    # the form that reserves a SIMD per wavefront (48-, 32- and 64-bit stored
+    # entries), 4, 8 and 10 windows per wavefront, with unrelated pairs mixed in
+    mixed = synth.make_batch("mixed_10kbp", indices=range(300, 324))
+    pats = [mixed.pat[mixed.pat_off[i]:mixed.pat_off[i + 1]].tobytes() for i in range(mixed.npairs)]
+    txts = [mixed.txt[mixed.txt_off[i]:mixed.txt_off[i + 1]].tobytes() for i in range(mixed.npairs)]
+    rng = np.random.default_rng(11)
+    for _ in range(6):
+        p, t = synth.random_pair(rng, 500, 520)
+        pats.append(p)
+        txts.append(t)
+    b = synth.from_lists(pats, txts)
+    ref = oracle.align_batch(b, W, O, W)
+    for slots in (4, 8, 10):
+        log(f"[parity] one wavefront per SIMD W={W} O={O} slots={slots}")
+        gpu = run_gpu(ctx, b, W=W, O=O, k=W, kernel="columns", slots=slots, one_per_simd=True)
+        compare(b, gpu, ref, f"one per SIMD W={W} O={O} slots={slots}")
+
+
+def test_one_wavefront_per_simd_queue_cycles(ctx):
+    # more wavefronts' worth of pairs than SIMDs: the capped grid takes pairs
+    # from the queue until it is empty
+    from paper_2208_09985_amd import api
+    b = synth.make_batch("small_100bp", 4 * 4 * ctx.cus + 300)
+    ref = oracle.align_batch(b, 64, 24, 64)
+    bt = api.Batch(ctx, b, api.params(kernel="columns", slots=4, one_per_simd=True))
+    shape = bt.launch_shape()
+    bt.close()
+    assert shape["one_per_simd"] and shape["grid"] == 4 * ctx.cus, shape
+    compare(b, run_gpu(ctx, b, kernel="columns", slots=4, one_per_simd=True), ref, "one per SIMD, queue cycles")
+
+
+def test_one_wavefront_per_simd_refused_forms(ctx):
+    from paper_2208_09985_amd import _lib as L, api
+    b = synth.make_batch("small_100bp", 16)
+    for kw in (dict(mode="learned"), dict(rows_lds=True), dict(store_edges=True), dict(row_ring=True),
+               dict(slots=16), dict(kernel="rows"), dict(kernel="lanes"), dict(W=96, O=24, k=96)):
+        prm = dict(kernel="columns", one_per_simd=True)
+        prm.update(kw)
+        with pytest.raises(L.ScgError) as e:
+            api.Batch(ctx, b, api.params(**prm))
+        assert e.value.code == L.EINVAL, (kw, e.value)
+
+
 @pytest.mark.parametrize("W,O", [(64, 24), (64, 40)])
 def test_ablation_flags_keep_results(ctx, W, O):
     # no early termination / all columns stored: more work, same alignments

@@ -63,6 +63,12 @@ def test_long_10kbp_all_pairs_plain_and_learned(ctx):
     w, b, ref = _workload("long_10kbp")
     # the headline launch as the benchmark runs it: a prepared batch, warm-up run, timed runs
     bt = api.Batch(ctx, b, api.params(W=w.W, O=w.O, k=w.k, mode="plain"))
+    shape = bt.launch_shape()
+    log(f"[full] long_10kbp plain launch shape {shape}")
+    if ctx.cus == 256:
+        # 1,250 wavefronts of 8 windows would not fit one per SIMD; 1,000 of 10 do
+        assert shape["kernel"] == "columns" and shape["slots"] == 10 and shape["one_per_simd"], shape
+        assert shape["grid"] == 1000 and shape["entry_bits"] == 48, shape
     for rep in range(2):
         log(f"[full] long_10kbp plain, benchmark launch, run {rep}")
         bt.edits.fill_(-7)
@@ -73,9 +79,10 @@ def test_long_10kbp_all_pairs_plain_and_learned(ctx):
     st = bt.stats()
     bt.close()
     assert st.windows == ref["stats"].windows and st.ops_alg == ref["stats"].ops_alg
-    for slots in (10, 16):
-        log(f"[full] long_10kbp plain, {slots} windows per wavefront")
-        compare(b, api.align_batch(ctx, b, kernel="columns", slots=slots), ref, f"long_10kbp full slots={slots}")
+    for slots, one in ((8, "auto"), (10, False), (16, "auto")):
+        log(f"[full] long_10kbp plain, {slots} windows per wavefront, one per SIMD: {one}")
+        compare(b, api.align_batch(ctx, b, kernel="columns", slots=slots, one_per_simd=one), ref,
+                f"long_10kbp full slots={slots} one_per_simd={one}")
     for kw in (dict(rows_lds=True), dict(row_ring=True), dict(kernel="lanes")):
         log(f"[full] long_10kbp plain, {kw}")
         compare(b, api.align_batch(ctx, b, **{"kernel": "columns", **kw}), ref, f"long_10kbp full {kw}")
