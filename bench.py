@@ -318,13 +318,19 @@ def main():
         workloads["window_sweep_long_10kbp"] = sweep
         # lanes per window in the column-block kernel: 16, 8, 4 or 2 lanes (4, 8, 16 or 32 windows per
         # wavefront); the error-row lane kernel's plain figure is in `variants`
+        # (10: six lanes of 12 columns), each with the automatic SIMD placement, and 8 and 10 also
+        # with wavefronts allowed to share a SIMD
         lanes = {}
-        for ng in (4, 8, 16, 32):
-            lms_, lst_, _ = measure(batch, f"columns, {ng} windows per wavefront",
-                                    api.params(W=w.W, O=w.O, k=w.k, mode="plain", kernel="columns", slots=ng), 5, 1)
+        for ng, one in ((4, "auto"), (8, "auto"), (8, False), (10, "auto"), (10, False), (16, "auto"), (32, "auto")):
+            tag = f"windows_per_wavefront_{ng}" + ("_shared_simds" if one is False else "")
+            lms_, lst_, _ = measure(batch, f"columns, {ng} windows per wavefront, one per SIMD {one}",
+                                    api.params(W=w.W, O=w.O, k=w.k, mode="plain", kernel="columns", slots=ng,
+                                               one_per_simd=one), 5, 1)
             e = summary(batch, lms_, lst_)
-            e["lanes_per_window"] = 64 // ng
-            lanes[f"windows_per_wavefront_{ng}"] = e
+            e["lanes_per_window"] = 6 if ng == 10 else 64 // ng
+            e["one_wavefront_per_simd"] = shapes[f"columns, {ng} windows per wavefront, one per SIMD {one}"]["one_per_simd"]
+            e["frac"] = round(lst_.ops_alg / (lst_.kernel_ms_avg / 1e3) / 1e12 / PEAK_T64OPS, 5)
+            lanes[tag] = e
         # the other end of the mapping: one lane per pair, rows in order (the paper's CPU mapping),
         # and the column-block kernel with its stored rows as a ring (DENT extended to rows) or with
         # the lowest rows in LDS
