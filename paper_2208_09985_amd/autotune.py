@@ -11,10 +11,13 @@ and keeps the fastest:
 * tau           -- learned mode: confidence needed before a smaller row budget
 * fixed_rows    -- fixed mode: constant row budget before falling back
 * rows_lds      -- plain mode: the lowest stored rows of each window in LDS
+* one_per_simd  -- plain mode: allow wavefronts to share a SIMD ("auto" reserves a
+                   whole SIMD per wavefront when they fit one per SIMD)
 
 Every candidate produces bit-identical output (the budget only changes how
 many rows are tried first), which the tuner checks against the first
-candidate.  Results are cached as JSON keyed by the device (CU count), the
+candidate; candidates that resolve to the same launch (the library reports
+it) are timed once.  Results are cached as JSON keyed by the device (CU count), the
 window parameters, the mode and a coarse signature of the batch (pair count
 and length distribution), so a later call with a similar batch reuses them.
 """
@@ -34,7 +37,7 @@ DEFAULT_CACHE = os.path.join(os.path.expanduser("~"), ".cache", "scrooge_mi355x"
 
 SPACE = {
     "plain": {"kernel": ["columns"], "slots": [4, 8, 10, 16], "waves_per_cu": [0], "order": ["input", "longest_first"],
-              "rows_lds": [False, True]},
+              "rows_lds": [False, True], "one_per_simd": ["auto", False]},
     "fixed": {"kernel": ["rows"], "slots": [2, 4, 6, 8], "waves_per_cu": [0], "order": ["input"],
               "fixed_rows": [7, 11, 15, 23]},
     "learned": {"kernel": ["rows", "columns"], "slots": [4, 8], "waves_per_cu": [0], "order": ["input"],
@@ -84,10 +87,18 @@ def tune(ctx, batch, W=64, O=24, k=64, mode="plain", space=None, reps=2, cache_p
     names = list(space)
     results = []
     ref = None
+    seen = {}
     for combo in itertools.product(*(space[n] for n in names)):
         cfg = dict(zip(names, combo))
         prm = api.params(W=W, O=O, k=k, mode=mode, **cfg)
         b = api.Batch(ctx, batch, prm)
+        # the same launch under another name: reuse its timing
+        launch = json.dumps([b.launch_shape(), {n: v for n, v in cfg.items() if n not in ("slots", "one_per_simd")}],
+                            sort_keys=True)
+        if launch in seen:
+            results.append(dict(seen[launch], cfg=cfg))
+            b.close()
+            continue
         b.run()
         torch.cuda.synchronize()
         b.stats()
@@ -102,6 +113,7 @@ def tune(ctx, batch, W=64, O=24, k=64, mode="plain", space=None, reps=2, cache_p
             raise RuntimeError(f"autotune: configuration {cfg} changed the output")
         results.append({"cfg": cfg, "kernel_ms": st.kernel_ms_avg, "fallback_windows": int(st.fallback_windows),
                         "rounds": int(st.rounds)})
+        seen[launch] = results[-1]
         if log:
             log(f"[autotune] {mode} {cfg}: {st.kernel_ms_avg:.3f} ms (fallback {st.fallback_windows}, "
                 f"rounds {st.rounds})")
