@@ -494,7 +494,10 @@ __global__ __launch_bounds__(64) void cols_kernel(const AlignArgs a) {
                     const int ti = tb_i + L, tj = tb_j + L, td = tb_d;
                     // edit step at (ti, tj, td): bits tj, tj+1 of row td-1 at columns ti and ti+1.
                     // The loads go out first; the run bookkeeping below overlaps them.
-                    uint64_t v0, v1, tb_de = 0;
+                    uint64_t v0 = 0, v1 = 0, tb_de = 0;
+                    // 32- and 48-bit forms: the loaded words as they are (low planes of
+                    // columns ti and ti+1; for 48 bits, their two high halves in one word)
+                    uint32_t w0 = 0, w1 = 0, wh = 0;
                     if constexpr (LR) {
                         const uint32_t rr = (uint32_t)(max(td, 1) - 1);
                         const uint32_t c0 = (uint32_t)min(ti, stride - 1), c1 = (uint32_t)min(ti + 1, stride - 1);
@@ -560,19 +563,20 @@ __global__ __launch_bounds__(64) void cols_kernel(const AlignArgs a) {
                         const char* const e0 = bdent + (ro + (uint32_t)min(ti, stride - 1) * ESZ);
                         const char* const e1 = bdent + (ro + (uint32_t)min(ti + 1, stride - 1) * ESZ);
                         if (NARROW) {
-                            v0 = *reinterpret_cast<const uint32_t*>(e0);
-                            v1 = *reinterpret_cast<const uint32_t*>(e1);
+                            w0 = *reinterpret_cast<const uint32_t*>(e0);
+                            w1 = *reinterpret_cast<const uint32_t*>(e1);
                         } else if (SPLIT) {
-                            // columns ti and ti+1 of both planes, as one 8-byte word each (the
-                            // 16-bit word from the 4-byte boundary at or below column ti)
-                            struct __attribute__((packed, aligned(4))) W2 { uint64_t v; };
+                            // columns ti and ti+1 of both planes, one 8-byte load per plane (the
+                            // 16-bit words from the 4-byte boundary at or below column ti)
+                            struct __attribute__((packed, aligned(4))) W2 { uint2 v; };
                             const uint32_t rr = slot_of((uint32_t)(max(td, 1) - 1));
                             const uint32_t c0 = (uint32_t)min(ti, stride - 1);
-                            const uint64_t lw = reinterpret_cast<const W2*>(bdent + (gbyte + __umul24(rr, lobytes) + c0 * 4u))->v;
-                            const uint64_t hw = reinterpret_cast<const W2*>(bdent + (hiplane + __umul24(rr, hibytes) + (c0 & ~1u) * 2u))->v
-                                                >> ((c0 & 1u) * 16u);
-                            v0 = (uint64_t)(uint32_t)lw | (uint64_t)(hw & 0xFFFFu) << 32;
-                            v1 = (lw >> 32) | (uint64_t)((hw >> 16) & 0xFFFFu) << 32;
+                            const uint2 lw = reinterpret_cast<const W2*>(bdent + (gbyte + __umul24(rr, lobytes) + c0 * 4u))->v;
+                            const uint2 hw = reinterpret_cast<const W2*>(bdent + (hiplane + __umul24(rr, hibytes) + (c0 & ~1u) * 2u))->v;
+                            w0 = lw.x;
+                            w1 = lw.y;
+                            // high halves of columns ti (bits 0..15) and ti+1 (bits 16..31)
+                            wh = __builtin_amdgcn_alignbit(hw.y, hw.x, (c0 & 1u) * 16u);
                         } else {
                             v0 = *reinterpret_cast<const uint64_t*>(e0);
                             v1 = *reinterpret_cast<const uint64_t*>(e1);
@@ -595,6 +599,29 @@ __global__ __launch_bounds__(64) void cols_kernel(const AlignArgs a) {
                         sb = has_t & (int)((v1 >> (tj & 63)) & 1ull);
                         ib = (int)((v0 >> (tj & 63)) & 1ull);
                         db = has_t & (int)((tb_de >> (tj & 63)) & 1ull);
+                    } else if constexpr (!LR && (NARROW || SPLIT)) {
+                        // W-O <= 47: an edit step has tj <= 46, so bits tj and tj+1 are stored
+                        // bits and no implicit bit 64 is read.  Bits tj.. of each entry: a
+                        // 32-bit entry shifted, or a 48-bit one funnel-shifted out of its high
+                        // half and low word (out of the high half alone from bit 32 on)
+                        const uint32_t sh = (uint32_t)tj & 31u;
+                        uint32_t a0, a1;
+                        if constexpr (NARROW) {
+                            a0 = w0 >> sh;
+                            a1 = w1 >> sh;
+                        } else {
+                            const bool up = tj >= 32;
+                            const uint32_t h1 = wh >> 16;
+                            a0 = __builtin_amdgcn_alignbit(wh, up ? wh : w0, sh);
+                            a1 = __builtin_amdgcn_alignbit(h1, up ? h1 : w1, sh);
+                        }
+                        // columns at or past n_w hold the initial column
+                        const uint32_t rcb = (uint32_t)(tb_rc >> (tj & 63));
+                        a0 = ti < nw ? a0 : rcb;                          // Z[ti][td-1] >> tj
+                        a1 = ti + 1 < nw ? a1 : rcb;                      // Z[ti+1][td-1] >> tj
+                        sb = has_t & (int)((a1 >> 1) & 1u);
+                        ib = (int)((a0 >> 1) & 1u);
+                        db = has_t & (int)(a1 & 1u);
                     } else {
                         const uint64_t za = ti < nw ? v0 : tb_rc;        // Z[ti][td-1]
                         const uint64_t zb = ti + 1 < nw ? v1 : tb_rc;    // Z[ti+1][td-1]
