@@ -104,6 +104,66 @@ __global__ __launch_bounds__(256) void pack_kernel(const uint8_t* __restrict__ s
     }
 }
 
+// Short sequences (up to kChunkWords words on average): one wavefront per
+// sequence instead of one workgroup, staging only the 16-byte blocks the
+// sequence covers and running the ballot loop over its own words only.  The
+// planes written are those of pack_kernel.
+__global__ __launch_bounds__(256) void pack_short_kernel(const uint8_t* __restrict__ seq,
+                                                         const int64_t* __restrict__ off,
+                                                         const int64_t* __restrict__ wordoff, int32_t npairs,
+                                                         int64_t total, Plane2* __restrict__ out,
+                                                         uint8_t* __restrict__ bad) {
+    __shared__ uint4 stage[4][kStageBlocks];
+    const int lane = threadIdx.x & 63;
+    const int wave = threadIdx.x >> 6;
+    const uint8_t* const sb = reinterpret_cast<const uint8_t*>(stage[wave]);
+    const uintptr_t sbase = reinterpret_cast<uintptr_t>(seq), send = sbase + (uintptr_t)total;
+    const int64_t nw_all = (int64_t)gridDim.x * 4;
+    for (int64_t s = (int64_t)blockIdx.x * 4 + wave; s < npairs; s += nw_all) {
+        const int64_t start = off[s];
+        const int64_t len = off[s + 1] - start;
+        const int64_t w0 = wordoff[s];
+        const int64_t nwords = wordoff[s + 1] - w0;   // (len + 63) / 64 + 1 padding word
+        uint32_t bad_lane = 0;
+        for (int64_t k0 = 0; k0 < nwords; k0 += kChunkWords) {
+            const uintptr_t p0 = sbase + (uintptr_t)(start + k0 * 64);
+            const uintptr_t a0 = p0 & ~(uintptr_t)15;
+            const int sh = (int)(p0 - a0);
+            const int rem = (int)max((int64_t)0, min(len - k0 * 64, (int64_t)(kChunkWords * 64)));
+            const int nblk = min(kStageBlocks, (sh + rem + 15) / 16);   // blocks holding the chunk's bases
+            for (int blk = lane; blk < nblk; blk += 64) {
+                const uintptr_t ba = a0 + 16u * (uintptr_t)blk;
+                uint4 v{0u, 0u, 0u, 0u};
+                if (ba < send) v = *reinterpret_cast<const uint4*>(ba);
+                stage[wave][blk] = v;
+            }
+            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+            __builtin_amdgcn_wave_barrier();
+            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+            uint32_t w_lo0 = 0, w_lo1 = 0, w_hi0 = 0, w_hi1 = 0;
+            const int nwc = (int)min((int64_t)kChunkWords, nwords - k0);   // words of this chunk (with the padding one)
+            for (int u = 0; u < nwc; ++u) {
+                const bool in = u * 64 + lane < rem;
+                // bytes past the chunk's bases are not staged: read them only when in
+                const uint32_t c = in ? sb[sh + u * 64 + lane] : 0u;
+                bad_lane |= in ? (is_base(c) ^ 1u) : 0u;
+                const uint64_t plo = __ballot(in && (c & 2u) != 0);
+                const uint64_t phi = __ballot(in && (c & 4u) != 0);
+                const bool mine = lane == u;
+                w_lo0 = mine ? (uint32_t)plo : w_lo0;
+                w_lo1 = mine ? (uint32_t)(plo >> 32) : w_lo1;
+                w_hi0 = mine ? (uint32_t)phi : w_hi0;
+                w_hi1 = mine ? (uint32_t)(phi >> 32) : w_hi1;
+            }
+            if (lane < nwc) out[w0 + k0 + lane] = Plane2{(uint64_t)w_lo1 << 32 | w_lo0, (uint64_t)w_hi1 << 32 | w_hi0};
+            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+            __builtin_amdgcn_wave_barrier();
+            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+        }
+        if (__ballot(bad_lane != 0) != 0 && lane == 0) bad[s] = 1;
+    }
+}
+
 }  // namespace
 
 hipError_t launch_reset(uint32_t* qctl, int32_t* ring, int64_t qcap, const int32_t* order,
@@ -119,6 +179,15 @@ hipError_t launch_reset(uint32_t* qctl, int32_t* ring, int64_t qcap, const int32
 hipError_t launch_pack(const uint8_t* seq, const int64_t* off, const int64_t* wordoff, int32_t npairs,
                        int64_t total_words, int64_t total_bytes, Plane2* out, uint8_t* bad, int num_cu, hipStream_t s) {
     if (total_words <= 0 || npairs <= 0) return hipSuccess;
+    if (total_words <= (int64_t)npairs * kChunkWords) {
+        // short sequences on average: a wavefront per sequence
+        int64_t blocks = ((int64_t)npairs + 3) / 4;
+        const int64_t cap = (int64_t)num_cu * 64;
+        if (blocks > cap) blocks = cap;
+        hipLaunchKernelGGL(pack_short_kernel, dim3((unsigned)blocks), dim3(256), 0, s, seq, off, wordoff, npairs,
+                           total_bytes, out, bad);
+        return hipGetLastError();
+    }
     int64_t blocks = npairs;
     const int64_t cap = (int64_t)num_cu * 64;           // grid-stride over sequences beyond this
     if (blocks > cap) blocks = cap;
