@@ -75,7 +75,10 @@ enum {
     SCG_MODE_FIXED = 2     /* constant budget (fixed_rows) per window, same fallback           */
 };
 
-enum { SCG_ORDER_INPUT = 0, SCG_ORDER_LONGEST_FIRST = 1 };
+/* queue order of the pairs (results do not depend on it): input order, longest
+ * (pattern + text) first, or automatic (the default of scg_params_default:
+ * longest first when the lengths' coefficient of variation exceeds 0.1) */
+enum { SCG_ORDER_INPUT = 0, SCG_ORDER_LONGEST_FIRST = 1, SCG_ORDER_AUTO = 2 };
 enum { SCG_WHERE_HOST = 0, SCG_WHERE_DEVICE = 1 };
 /* input_kind of the batch calls: how pattern and text bytes are encoded */
 enum {
@@ -282,7 +285,8 @@ int scg_ops_to_cigar(const uint8_t* ops, int32_t n_ops, char* cigar, int32_t cap
  * For callers that cannot allocate device memory (code under HIP graph
  * capture, tight serving loops, harnesses that forbid hipMalloc): the same
  * alignment and run-word output as scg_batch_create + scg_batch_run in plain
- * mode (column-block kernel, input order, W <= 64, no yields, flags 0) on
+ * mode (column-block kernel, input order: order SCG_ORDER_INPUT or SCG_ORDER_AUTO,
+ * W <= 64, no yields, flags 0) on
  * device input, in one call, with every buffer besides the caller's
  * inputs and outputs taken from a static device workspace of fixed size that
  * each device holds for the life of the process (SCG_NOALLOC_DENT_MIB MiB of

@@ -15,7 +15,7 @@ OK, EINVAL, EALPHABET, ERANGE, ENOMEM, EDEVICE, ENOMODEL, EINTERNAL, ELIMIT = 0,
 NOALLOC_MAX_PAIRS, NOALLOC_MAX_BASES = 65536, 67108864
 PAIR_OK, PAIR_NOT_ALIGNED, PAIR_BAD_INPUT, PAIR_ERROR = 0, 1, 2, 3
 MODE_PLAIN, MODE_LEARNED, MODE_FIXED = 0, 1, 2
-ORDER_INPUT, ORDER_LONGEST_FIRST = 0, 1
+ORDER_INPUT, ORDER_LONGEST_FIRST, ORDER_AUTO = 0, 1, 2
 WHERE_HOST, WHERE_DEVICE = 0, 1
 INPUT_ASCII, INPUT_PACKED2 = 0, 1
 FLAG_GRAPH = 1

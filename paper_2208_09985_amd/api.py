@@ -32,7 +32,7 @@ def _stream_ptr(stream) -> ctypes.c_void_p:
     return ctypes.c_void_p(stream.cuda_stream)
 
 
-def params(W=64, O=24, k=64, mode="plain", slots=0, waves_per_cu=0, order="input", fixed_rows=None, tau=None,
+def params(W=64, O=24, k=64, mode="plain", slots=0, waves_per_cu=0, order="auto", fixed_rows=None, tau=None,
            graph=False, yield_chars=None, kernel="auto", no_early_termination=False,
            store_all_columns=False, rows_lds=False, store_edges=False, row_ring=False,
            one_per_simd="auto") -> L.Params:
@@ -41,7 +41,7 @@ def params(W=64, O=24, k=64, mode="plain", slots=0, waves_per_cu=0, order="input
     p.W, p.O, p.k = W, O, k
     p.mode = {"plain": L.MODE_PLAIN, "learned": L.MODE_LEARNED, "fixed": L.MODE_FIXED}[mode]
     p.slots, p.waves_per_cu = slots, waves_per_cu
-    p.order = {"input": L.ORDER_INPUT, "longest_first": L.ORDER_LONGEST_FIRST}[order]
+    p.order = {"input": L.ORDER_INPUT, "longest_first": L.ORDER_LONGEST_FIRST, "auto": L.ORDER_AUTO}[order]
     if fixed_rows is not None:
         p.fixed_rows = fixed_rows
     if tau is not None:

@@ -129,7 +129,8 @@ int check_params(const scg_params* p) {
     const bool cols = p->kernel == SCG_KERNEL_COLUMNS || (p->kernel == SCG_KERNEL_AUTO && p->mode == SCG_MODE_PLAIN);
     const int max_slots = cols && p->mode != SCG_MODE_LEARNED ? 32 : kMaxSlots;
     if (p->slots < 0 || p->slots > max_slots || p->waves_per_cu < 0) return SCG_EINVAL;
-    if (p->order != SCG_ORDER_INPUT && p->order != SCG_ORDER_LONGEST_FIRST) return SCG_EINVAL;
+    if (p->order != SCG_ORDER_INPUT && p->order != SCG_ORDER_LONGEST_FIRST && p->order != SCG_ORDER_AUTO)
+        return SCG_EINVAL;
     if (p->mode == SCG_MODE_FIXED && (p->fixed_rows < 1 || p->fixed_rows > 64)) return SCG_EINVAL;
     if (p->mode == SCG_MODE_LEARNED && !(p->tau > 0.f && p->tau <= 1.f)) return SCG_EINVAL;
     if (p->yield_chars > 0 && p->yield_chars < p->W - p->O) return SCG_EINVAL;
@@ -340,7 +341,7 @@ void scg_params_default(scg_params* p) {
     p->O = 24;
     p->k = 64;
     p->mode = SCG_MODE_PLAIN;
-    p->order = SCG_ORDER_INPUT;
+    p->order = SCG_ORDER_AUTO;
     p->fixed_rows = 15;
     p->tau = 0.8f;
     p->yield_chars = -1;
@@ -539,7 +540,20 @@ int scg_batch_create(scg_ctx* c, const scg_params* params, int32_t npairs, const
         for (int32_t i = 0; i < npairs; ++i) b->qcap += pl[i] / b->p.yield_chars + 1;
     std::vector<int32_t> order(npairs);
     std::iota(order.begin(), order.end(), 0);
-    if (params->order == SCG_ORDER_LONGEST_FIRST)
+    // automatic order: longest first when the pairs' lengths differ by more than a
+    // tenth (coefficient of variation), so that long pairs do not start last
+    bool longest_first = params->order == SCG_ORDER_LONGEST_FIRST;
+    if (params->order == SCG_ORDER_AUTO && npairs > 1) {
+        double sum = 0.0, sq = 0.0;
+        for (int32_t i = 0; i < npairs; ++i) {
+            const double l = (double)pl[i] + (double)tl[i];
+            sum += l;
+            sq += l * l;
+        }
+        const double mean = sum / npairs, var = std::max(0.0, sq / npairs - mean * mean);
+        longest_first = mean > 0.0 && std::sqrt(var) > 0.1 * mean;
+    }
+    if (longest_first)
         std::stable_sort(order.begin(), order.end(),
                          [&](int32_t x, int32_t y) { return (int64_t)pl[x] + tl[x] > (int64_t)pl[y] + tl[y]; });
     // device workspace

@@ -174,9 +174,10 @@ extern "C" int scg_align_batch_noalloc(scg_ctx* c, const scg_params* params, int
     if (!c || npairs < 0 || pat_total < 0 || txt_total < 0) return SCG_EINVAL;
     int rc = capi_check_params(params);
     if (rc) return rc;
-    // plain mode in the column-block kernel, input order, no yields or flags
+    // plain mode in the column-block kernel, input order (automatic order means input
+    // order here), no yields or flags
     if (params->mode != SCG_MODE_PLAIN || params->W > 64 || params->kernel == SCG_KERNEL_ROWS ||
-        params->order != SCG_ORDER_INPUT || params->yield_chars > 0 || params->flags != 0)
+        params->order == SCG_ORDER_LONGEST_FIRST || params->yield_chars > 0 || params->flags != 0)
         return SCG_EINVAL;
     if (npairs > kMaxPairs || pat_total > kMaxBases || txt_total > kMaxBases) return SCG_ELIMIT;
     if (npairs == 0) return SCG_OK;

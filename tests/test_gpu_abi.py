@@ -74,6 +74,24 @@ def test_window_and_launch_ranges(kw):
     assert e.value.code == L.EINVAL, kw
 
 
+def test_queue_order_values(ctx):
+    # the automatic order (the default) sorts uneven batches longest first and keeps
+    # equal-length ones in input order; results never depend on the order
+    import oracle
+    from tests.gpu_helpers import compare
+    from paper_2208_09985_amd import api, _lib as L
+    b = synth.make_batch("uneven_lognormal", 48)
+    ref = oracle.align_batch(b, 64, 24, 64)
+    for order in ("auto", "input", "longest_first"):
+        compare(b, api.align_batch(ctx, b, order=order), ref, f"order {order}")
+    p = api.params()
+    assert p.order == L.ORDER_AUTO
+    p.order = 3
+    with pytest.raises(L.ScgError) as e:
+        api.Batch(ctx, b, p)
+    assert e.value.code == L.EINVAL
+
+
 def test_single_pair_cigar_buffer_too_small(ctx):
     lib = ctx._lib
     from paper_2208_09985_amd import _lib as L
