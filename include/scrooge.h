@@ -138,13 +138,25 @@ typedef struct {
                             /* < 0: automatic, 1280 for error-row lanes, 0 for column  */
                             /* blocks)                                                 */
     int32_t kernel;         /* SCG_KERNEL_*                                            */
-    int32_t one_per_simd;   /* column blocks, plain mode, rows in global memory, 4, 8  */
-                            /* or 10 windows per wavefront: 1 = the form that holds a  */
+    int32_t one_per_simd;   /* column blocks, plain mode, rows in global memory, 4, 8, */
+                            /* 10 or 16 windows per wavefront: 1 = the form that holds a */
                             /* whole SIMD per wavefront (the grid is then at most one  */
                             /* wavefront per SIMD); 0 = automatic, that form whenever  */
                             /* the batch's wavefronts fit one per SIMD (10 windows per */
                             /* wavefront are then picked when 8 would not fit); -1 =   */
                             /* never.  Results are the same either way                 */
+    int32_t offtrack_helpers;  /* column blocks, plain mode, rows in global memory, no    */
+                            /* yields, ablations or graph: a pair whose last three     */
+                            /* windows each had d_w >= (W-O)/2 (it has lost the        */
+                            /* diagonal) is handed to a second launch of wavefronts    */
+                            /* with 4 windows of 16 lanes each, on the SIMDs the main  */
+                            /* launch (16 windows per wavefront, one per SIMD) leaves  */
+                            /* free; its windows then take fewer instructions.  1 =    */
+                            /* always when the main launch fits, 0 = automatic (pairs  */
+                            /* longer than 32 windows on average, more pairs than      */
+                            /* 8-window wavefronts one per SIMD can hold, and 16-window */
+                            /* wavefronts that fit while leaving at least 128 SIMDs),  */
+                            /* -1 = never.  Results are the same either way            */
 } scg_params;
 
 typedef struct {
@@ -228,7 +240,9 @@ int scg_batch_runs_offsets(const scg_batch* b, int64_t* out);
  * out[2] wavefronts in the grid; out[3] dynamic LDS bytes per wavefront;
  * out[4] 1 for the form holding a whole SIMD per wavefront; out[5] stored
  * entry bits (32, 48 or 64; 96 or 128 for wide windows; 0 for error-row
- * lanes).  out: 6 int32 in host memory.  Errors: SCG_EINVAL. */
+ * lanes); out[6] wavefronts of the off-track helper launch (0: none);
+ * out[7] its windows per wavefront.  out: 8 int32 in host memory.
+ * Errors: SCG_EINVAL. */
 int scg_batch_launch_shape(const scg_batch* b, int32_t* out);
 
 /* Align the batch: encode+pack (Section 2.5's 2-bit encoding), then the

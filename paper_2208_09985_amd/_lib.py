@@ -46,6 +46,7 @@ class Params(ctypes.Structure):
         ("order", ctypes.c_int32), ("fixed_rows", ctypes.c_int32), ("tau", ctypes.c_float),
         ("flags", ctypes.c_int32), ("yield_chars", ctypes.c_int32), ("kernel", ctypes.c_int32),
         ("one_per_simd", ctypes.c_int32),
+        ("offtrack_helpers", ctypes.c_int32),
     ]
 
 

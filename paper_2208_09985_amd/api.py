@@ -35,7 +35,7 @@ def _stream_ptr(stream) -> ctypes.c_void_p:
 def params(W=64, O=24, k=64, mode="plain", slots=0, waves_per_cu=0, order="auto", fixed_rows=None, tau=None,
            graph=False, yield_chars=None, kernel="auto", no_early_termination=False,
            store_all_columns=False, rows_lds=False, store_edges=False, row_ring=False,
-           one_per_simd="auto") -> L.Params:
+           one_per_simd="auto", offtrack_helpers="auto") -> L.Params:
     p = L.Params()
     L.load().scg_params_default(ctypes.byref(p))
     p.W, p.O, p.k = W, O, k
@@ -54,6 +54,7 @@ def params(W=64, O=24, k=64, mode="plain", slots=0, waves_per_cu=0, order="auto"
     p.kernel = {"auto": L.KERNEL_AUTO, "rows": L.KERNEL_ROWS, "columns": L.KERNEL_COLUMNS,
                 "lanes": L.KERNEL_LANES}[kernel]
     p.one_per_simd = {"auto": 0, True: 1, False: -1}[one_per_simd]
+    p.offtrack_helpers = {"auto": 0, True: 1, False: -1}[offtrack_helpers]
     return p
 
 
@@ -185,11 +186,11 @@ class Batch:
         L.check(rc, "scg_batch_run")
 
     def launch_shape(self) -> dict:
-        out = (ctypes.c_int32 * 6)()
+        out = (ctypes.c_int32 * 8)()
         L.check(self._lib.scg_batch_launch_shape(self.handle, out), "scg_batch_launch_shape")
         kernel = {L.KERNEL_ROWS: "rows", L.KERNEL_COLUMNS: "columns", L.KERNEL_LANES: "lanes", 4: "wide"}[out[0]]
         return {"kernel": kernel, "slots": out[1], "grid": out[2], "lds_bytes": out[3], "one_per_simd": bool(out[4]),
-                "entry_bits": out[5]}
+                "entry_bits": out[5], "helper_grid": out[6], "helper_slots": out[7]}
 
     def stats(self) -> L.Stats:
         st = L.Stats()

@@ -160,7 +160,13 @@ __global__ __launch_bounds__(64) void cols_kernel(const AlignArgs a) {
     int mw = 0, nw = 0, kw = 0;
     int64_t roff = 0, rcap = 0, pending = -1;
     int polled = 0;
+    int deep_run = 0;   // slot lane: consecutive windows of the pair with d_w >= mig_d
     bool exhausted = !slot;
+    // the queue this launch takes pairs from: the main ring, or (helper) hring
+    uint32_t* const qhead = a.helper ? &a.qctl[kQcHHead] : &a.qctl[0];
+    const int32_t* const qring = a.helper ? a.hring : a.ring;
+    const int64_t qcapv = a.helper ? (int64_t)a.npairs : a.qcap;
+    uint32_t idle = 0, beat = 0;
     unsigned long long c_windows = 0, c_ops = 0, c_fallback = 0, c_rows = 0, c_err = 0, c_yield = 0;
     int tb_i = 0, tb_j = 0, tb_d = 0, tb_e = 0, tb_bad = 0;   // slot lane: traceback position and edits
     uint64_t tb_rc = 0;   // slot lane: the initial column at row tb_d - 1 (Z beyond the text window)
@@ -180,14 +186,14 @@ __global__ __launch_bounds__(64) void cols_kernel(const AlignArgs a) {
     for (;;) {
         // ---- 1. slot lanes take pairs from the queue ----
         if (!exhausted && pair < 0) {
-            if (pending < 0) pending = (int64_t)atomicAdd(&a.qctl[0], 1u);
-            if (pending >= a.qcap) {
+            if (pending < 0) pending = (int64_t)atomicAdd(qhead, 1u);
+            if (pending >= qcapv) {
                 exhausted = true;
             } else {
-                polled = __hip_atomic_load(&a.ring[pending], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                polled = __hip_atomic_load(&qring[pending], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
                 if (polled != 0) {
                     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
-                    const bool fresh = pending < a.npairs;
+                    const bool fresh = !a.helper && pending < a.npairs;   // hring holds handed-over pairs only
                     const int pid = polled - 1;
                     pending = -1;
                     polled = 0;
@@ -210,6 +216,7 @@ __global__ __launch_bounds__(64) void cols_kernel(const AlignArgs a) {
                             p0 = st[0]; t0 = st[1]; edits = st[2]; nruns = st[3]; cur_op = st[4]; cur_len = st[5];
                         }
                         p0_take = p0;
+                        deep_run = 0;
                         roff = a.runs_off[pid];
                         rcap = a.runs_off[pid + 1] - roff;
                     }
@@ -320,6 +327,28 @@ __global__ __launch_bounds__(64) void cols_kernel(const AlignArgs a) {
             // can ever receive one; otherwise wait for yielded pairs
             const bool waiting = !exhausted && pair < 0;
             if (__ballot(waiting) == 0) break;
+            if (a.helper) {
+                // a helper waits for handed-over pairs while the main launch runs: its
+                // slots poll their own hring entries; the shared counters are read once
+                // every 16 sleeps, and it leaves after idle_limit such reads in which the
+                // main launch showed no beat
+                idle += 1u;
+                if ((idle & 15u) != 0u) {
+                    __builtin_amdgcn_s_sleep(32);
+                    continue;
+                }
+                if (__hip_atomic_load(&a.qctl[2], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) >= (uint32_t)a.npairs)
+                    break;
+                const uint32_t b = __hip_atomic_load(&a.qctl[kQcBeat], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                if (b != beat) {
+                    beat = b;
+                    idle = 0u;
+                } else if ((idle >> 4) > (uint32_t)a.idle_limit) {
+                    break;
+                }
+                __builtin_amdgcn_s_sleep(32);
+                continue;
+            }
             if (__hip_atomic_load(&a.qctl[2], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) >= (uint32_t)a.npairs) break;
             __builtin_amdgcn_s_sleep(16);
             continue;
@@ -440,6 +469,8 @@ __global__ __launch_bounds__(64) void cols_kernel(const AlignArgs a) {
         } while (__ballot(gst == G_RUN) != 0);
         c_lane_steps += 64ull * (unsigned long long)steps;
         c_rounds += 1;
+        // the main launch's beat for the helpers, every 32 passes of a wavefront
+        if (a.mig_k > 0 && lane == 0 && (c_rounds & 31u) == 0u) atomicAdd(&a.qctl[kQcBeat], 1u);
         // the group's stored rows are read by its slot lane
         __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
         __syncthreads();
@@ -464,10 +495,12 @@ __global__ __launch_bounds__(64) void cols_kernel(const AlignArgs a) {
                 a.n_runs[pair] = 0;
                 pair = -1;
                 atomicAdd(&a.qctl[2], 1u);
+                if (a.helper) atomicSub(&a.qctl[kQcHInFlight], 1u);
                 gst = G_EMPTY;
             } else {
                 c_windows += 1;
                 c_ops += (unsigned long long)(tb_d + 1) + 2ull * nw + 7ull * nw * tb_d;
+                deep_run = tb_d >= a.mig_d ? deep_run + 1 : 0;
                 tb_i = tb_j = tb_e = tb_bad = 0;
                 tb_rc = z_init(mw, tb_d - 1);
             }
@@ -665,6 +698,22 @@ __global__ __launch_bounds__(64) void cols_kernel(const AlignArgs a) {
                     a.n_runs[pair] = ok ? nruns : 0;
                     pair = -1;
                     atomicAdd(&a.qctl[2], 1u);
+                    if (a.helper) atomicSub(&a.qctl[kQcHInFlight], 1u);
+                } else if (a.mig_k > 0 && deep_run >= a.mig_k) {
+                    // off track: hand the pair to the helper launch, which gives a window
+                    // more lanes (each pair moves at most once, so hring never overflows)
+                    if (atomicAdd(&a.qctl[kQcHInFlight], 1u) < (uint32_t)a.mig_cap) {
+                        const uint32_t tq = atomicAdd(&a.qctl[kQcHTail], 1u);
+                        int32_t* st = a.pstate + 8 * (int64_t)pair;
+                        st[0] = p0; st[1] = t0; st[2] = edits; st[3] = nruns; st[4] = cur_op; st[5] = cur_len;
+                        st[6] = 0; st[7] = 0;
+                        __hip_atomic_store(&a.hring[tq], pair + 1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+                        pair = -1;
+                        c_yield += 1;
+                    } else {
+                        atomicSub(&a.qctl[kQcHInFlight], 1u);
+                        deep_run = 0;   // the helpers are full: try again after mig_k more deep windows
+                    }
                 } else if (a.yield_chars > 0 && p0 - p0_take >= a.yield_chars) {
                     // hand the pair back to the queue between windows
                     const uint32_t tq = atomicAdd(&a.qctl[1], 1u);
@@ -759,17 +808,18 @@ static const void* cols_fn_plain(int ng, int sm) {
     return cols_fn<false, ST>(ng);
 }
 
-// the one-wavefront-per-SIMD forms: plain mode, rows in global memory, 4, 8 or
-// 10 windows per wavefront
+// the one-wavefront-per-SIMD forms: plain mode, rows in global memory, 4, 8,
+// 10 or 16 windows per wavefront
 template <int ST>
 static const void* cols_fn_one(int ng) {
     if (ng == 4) return (const void*)cols_kernel<false, 4, ST, 0, true>;
     if (ng == 8) return (const void*)cols_kernel<false, 8, ST, 0, true>;
+    if (ng == 16) return (const void*)cols_kernel<false, 16, ST, 0, true>;
     return (const void*)cols_kernel<false, 10, ST, 0, true>;
 }
 
 bool cols_one_per_simd_ok(bool learned, int ng, int sm, bool edges) {
-    return !learned && !edges && sm == 0 && (ng == 4 || ng == 8 || ng == 10);
+    return !learned && !edges && sm == 0 && (ng == 4 || ng == 8 || ng == 10 || ng == 16);
 }
 
 // the edge-storing ablation form: plain mode, 4, 8 or 16 windows per wavefront
@@ -813,6 +863,7 @@ hipError_t launch_align_cols(const AlignArgs& a, int grid, int ng, size_t lds, h
     do {                                                                                           \
         if (ng == 4) hipLaunchKernelGGL((cols_kernel<false, 4, STV, 0, true>), dim3(grid), dim3(64), lds, s, a);       \
         else if (ng == 8) hipLaunchKernelGGL((cols_kernel<false, 8, STV, 0, true>), dim3(grid), dim3(64), lds, s, a);  \
+        else if (ng == 16) hipLaunchKernelGGL((cols_kernel<false, 16, STV, 0, true>), dim3(grid), dim3(64), lds, s, a); \
         else hipLaunchKernelGGL((cols_kernel<false, 10, STV, 0, true>), dim3(grid), dim3(64), lds, s, a);              \
     } while (0)
 #define SCG_COLS_PLAIN(STV)                                  \

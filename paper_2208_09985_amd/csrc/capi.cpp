@@ -33,6 +33,13 @@ struct scg_ctx {
 struct scg_batch {
     scg_ctx* ctx = nullptr;
     bool one = false;   // column blocks: one wavefront per SIMD
+    // off-track helpers: a second launch of 4-window wavefronts on its own stream
+    int help_grid = 0;
+    uint64_t* help_dent_d = nullptr;
+    int32_t* hring_d = nullptr;
+    int mig_k = 0, mig_d = 0, mig_cap = 0;
+    hipStream_t s2 = nullptr;
+    hipEvent_t fork_ev = nullptr, join_ev = nullptr;
     scg_params p{};
     int32_t npairs = 0;
     // sequences (ASCII) on the device
@@ -156,9 +163,17 @@ int check_params(const scg_params* p) {
     // a whole SIMD per wavefront: plain mode in the column-block kernel, rows in
     // global memory, 4, 8 or 10 windows per wavefront
     if (p->one_per_simd < -1 || p->one_per_simd > 1) return SCG_EINVAL;
+    if (p->offtrack_helpers < -1 || p->offtrack_helpers > 1) return SCG_EINVAL;
+    // off-track helpers forced: plain mode in the column-block kernel, rows in global
+    // memory, no yields, ablations or graph, 8, 10 or 16 windows per main wavefront
+    if (p->offtrack_helpers == 1 &&
+        (p->mode != SCG_MODE_PLAIN || p->W > 64 || p->kernel == SCG_KERNEL_ROWS || p->kernel == SCG_KERNEL_LANES ||
+         p->flags != 0 || p->yield_chars > 0 || p->one_per_simd < 0 ||
+         (p->slots != 0 && p->slots != 8 && p->slots != 10 && p->slots != 16)))
+        return SCG_EINVAL;
     if (p->one_per_simd == 1 &&
         (p->mode != SCG_MODE_PLAIN || p->W > 64 || p->kernel == SCG_KERNEL_ROWS || p->kernel == SCG_KERNEL_LANES ||
-         (p->flags & (SCG_FLAG_ROWS_LDS | SCG_FLAG_STORE_EDGES | SCG_FLAG_ROW_RING)) || p->slots > 10))
+         (p->flags & (SCG_FLAG_ROWS_LDS | SCG_FLAG_STORE_EDGES | SCG_FLAG_ROW_RING)) || p->slots > 16))
         return SCG_EINVAL;
     return SCG_OK;
 }
@@ -170,9 +185,13 @@ void free_batch(scg_batch* b) {
     for (auto& trip : b->ev)
         for (auto& e : trip)
             if (e) (void)hipEventDestroy(e);
+    if (b->fork_ev) (void)hipEventDestroy(b->fork_ev);
+    if (b->join_ev) (void)hipEventDestroy(b->join_ev);
+    if (b->s2) (void)hipStreamDestroy(b->s2);
     void* ptrs[] = {b->own_seq ? b->pat_d : nullptr, b->own_seq ? b->txt_d : nullptr, b->pat_off_d, b->txt_off_d,
                     b->pplanes, b->tplanes, b->pword_d, b->tword_d, b->plen_d, b->tlen_d, b->bad_d, b->order_d,
-                    b->runs_off_d, b->qctl_d, b->ring_d, b->pstate_d, b->stats_d, b->dent_d, b->pin_d, b->tin_d};
+                    b->runs_off_d, b->qctl_d, b->ring_d, b->pstate_d, b->stats_d, b->dent_d, b->pin_d, b->tin_d,
+                    b->help_dent_d, b->hring_d};
     for (void* q : ptrs)
         if (q) (void)hipFree(q);
     delete b;
@@ -204,7 +223,7 @@ int enqueue_run(scg_batch* b, hipStream_t s, int32_t* edits, int32_t* text_end, 
             if (!ev[i]) HIP_TRY(hipEventCreate(&ev[i]));
         HIP_TRY(hipEventRecord(ev[0], s));
     }
-    HIP_TRY(launch_reset(b->qctl_d, b->ring_d, b->qcap, b->order_d, b->stats_d, b->bad_d, b->npairs, s));
+    HIP_TRY(launch_reset(b->qctl_d, b->ring_d, b->qcap, b->order_d, b->stats_d, b->bad_d, b->npairs, s, b->hring_d));
     int prc = enqueue_pack(b, s);
     if (prc) return prc;
     if (with_events) HIP_TRY(hipEventRecord(ev[1], s));
@@ -257,10 +276,31 @@ int enqueue_run(scg_batch* b, hipStream_t s, int32_t* edits, int32_t* text_end, 
     a.ring_rows = b->ring_rows;
     a.no_et = (b->p.flags & SCG_FLAG_NO_EARLY_TERMINATION) ? 1 : 0;
     a.one_per_simd = b->one ? 1 : 0;
+    a.hring = b->hring_d;
+    a.mig_k = b->help_grid > 0 ? b->mig_k : 0;
+    a.mig_d = b->mig_d;
+    a.mig_cap = b->mig_cap;
+    a.helper = 0;
+    a.idle_limit = 1 << 12;   // about 4096 x 16 sleeps of 32 x 64 cycles: some 55 ms with no main beat
     if (b->npairs > 0) {
         if (b->lanes) HIP_TRY(launch_align_lane(a, b->grid, s));
         else if (b->wide) HIP_TRY(launch_align_wide(a, b->grid, b->ns, s));
-        else if (b->cols) HIP_TRY(launch_align_cols(a, b->grid, b->ns, b->lds, s));
+        else if (b->cols && b->help_grid > 0) {
+            // main launch on s, helper launch on s2 after the queues are reset, joined back into s
+            HIP_TRY(hipEventRecord(b->fork_ev, s));
+            HIP_TRY(launch_align_cols(a, b->grid, b->ns, b->lds, s));
+            HIP_TRY(hipStreamWaitEvent(b->s2, b->fork_ev, 0));
+            AlignArgs h = a;
+            h.helper = 1;
+            h.mig_k = 0;
+            h.yield_chars = 0;
+            h.ns = kHelperSlots;
+            h.dent = b->help_dent_d;
+            h.dstride = cols_dent_stride(a.cap, kHelperSlots);
+            HIP_TRY(launch_align_cols(h, b->help_grid, kHelperSlots, 0, b->s2));
+            HIP_TRY(hipEventRecord(b->join_ev, b->s2));
+            HIP_TRY(hipStreamWaitEvent(s, b->join_ev, 0));
+        } else if (b->cols) HIP_TRY(launch_align_cols(a, b->grid, b->ns, b->lds, s));
         else HIP_TRY(launch_align(a, b->grid, b->lds, s));
     }
     if (with_events) {
@@ -566,7 +606,7 @@ int scg_batch_create(scg_ctx* c, const scg_params* params, int32_t npairs, const
         (rc = dev_alloc(&b->pword_d, npairs + 1)) || (rc = dev_alloc(&b->tword_d, npairs + 1)) ||
         (rc = dev_alloc(&b->plen_d, npairs)) || (rc = dev_alloc(&b->tlen_d, npairs)) ||
         (rc = dev_alloc(&b->bad_d, npairs)) || (rc = dev_alloc(&b->order_d, npairs)) ||
-        (rc = dev_alloc(&b->runs_off_d, npairs + 1)) || (rc = dev_alloc(&b->qctl_d, 4)) ||
+        (rc = dev_alloc(&b->runs_off_d, npairs + 1)) || (rc = dev_alloc(&b->qctl_d, kQcWords)) ||
         (rc = dev_alloc(&b->ring_d, (size_t)b->qcap)) || (rc = dev_alloc(&b->pstate_d, (size_t)npairs * 8)) ||
         (rc = dev_alloc(&b->stats_d, ST_COUNT)))
         return fail(rc);
@@ -633,8 +673,33 @@ int scg_batch_create(scg_ctx* c, const scg_params* params, int32_t npairs, const
         else if (npairs < 8 * c->num_cu) b->ns = 4;
         else if (waves(8) > simds && waves(10) <= simds && plain_global && params->one_per_simd >= 0) b->ns = 10;
         else b->ns = 8;
-        b->one = plain_global && (b->ns == 4 || b->ns == 8 || b->ns == 10) &&
+        b->one = plain_global && (b->ns == 4 || b->ns == 8 || b->ns == 10 || b->ns == 16) &&
                  (params->one_per_simd == 1 || (params->one_per_simd == 0 && waves(b->ns) <= simds));
+        // Off-track helpers.  A pair that has lost the diagonal keeps d_w near W-O in
+        // every window, and such pairs set the kernel's time; a second launch of
+        // 4-window wavefronts (16 lanes of 4 columns) on the SIMDs the main launch
+        // leaves free takes them over.  The main launch then runs 16 windows per
+        // wavefront (unless slots says otherwise), one wavefront per SIMD.
+        {
+            const bool ok = params->mode == SCG_MODE_PLAIN && params->flags == 0 && params->yield_chars <= 0 &&
+                            params->one_per_simd >= 0 && params->offtrack_helpers >= 0;
+            const int mng = params->slots > 0 ? b->ns : 16;
+            const int64_t mwaves = waves(mng);
+            int64_t total_m = 0;
+            for (int32_t i = 0; i < npairs; ++i) total_m += pl[i];
+            const bool long_pairs = npairs > 0 && total_m / npairs >= 32LL * (params->W - params->O);
+            const bool fits = (mng == 8 || mng == 10 || mng == 16) && mwaves + 1 <= simds;
+            const bool want = params->offtrack_helpers == 1 ||
+                              (long_pairs && waves(8) > simds && mwaves + 128 <= simds);
+            if (ok && fits && want) {
+                b->ns = mng;
+                b->one = true;
+                b->help_grid = (int)std::min<int64_t>(simds - mwaves, ((int64_t)npairs + kHelperSlots - 1) / kHelperSlots);
+                b->mig_k = 3;
+                b->mig_d = std::max(1, (params->W - params->O) / 2);
+                b->mig_cap = b->help_grid * kHelperSlots;
+            }
+        }
         // SCG_FLAG_ROWS_LDS: the lowest stored rows of each window in LDS, as
         // many as fit while every wavefront the batch needs (or the
         // register-limited maximum) stays resident on its CU
@@ -692,6 +757,15 @@ int scg_batch_create(scg_ctx* c, const scg_params* params, int32_t npairs, const
         if ((rc = dev_alloc(&b->dent_d, cols_dent_bytes(b->grid, scap, b->ns, edges, b->ring_rows) / sizeof(uint64_t))))
             return fail(rc);
     }
+    if (b->cols && npairs > 0 && b->help_grid > 0) {
+        const int cap = params->W - params->O;
+        if ((rc = dev_alloc(&b->help_dent_d, cols_dent_bytes(b->help_grid, cap, kHelperSlots, false, 0) / sizeof(uint64_t))) ||
+            (rc = dev_alloc(&b->hring_d, (size_t)npairs)) ||
+            (rc = from_hip(hipStreamCreateWithFlags(&b->s2, hipStreamNonBlocking))) ||
+            (rc = from_hip(hipEventCreateWithFlags(&b->fork_ev, hipEventDisableTiming))) ||
+            (rc = from_hip(hipEventCreateWithFlags(&b->join_ev, hipEventDisableTiming))))
+            return fail(rc);
+    }
     *out = b;
     return SCG_OK;
 }
@@ -712,6 +786,8 @@ int scg_batch_launch_shape(const scg_batch* b, int32_t* out) {
     out[2] = b->grid;
     out[3] = (int32_t)b->lds;
     out[4] = b->one ? 1 : 0;
+    out[6] = b->help_grid;
+    out[7] = b->help_grid > 0 ? kHelperSlots : 0;
     if (b->wide) out[5] = cap <= 95 ? 96 : 128;
     else if (b->cols) out[5] = (b->p.flags & SCG_FLAG_STORE_EDGES) || learned ? 64 : (cap <= 31 ? 32 : (cap <= 47 ? 48 : 64));
     else if (b->lanes) out[5] = 64;
@@ -971,7 +1047,7 @@ int scg_features(scg_batch* b, int32_t nwin, const int32_t* windows, uint16_t* f
     HIP_TRY(hipSetDevice(b->ctx->device));
     hipStream_t s = (hipStream_t)stream;
     // planes are produced by the pack step of a run; make sure they exist
-    HIP_TRY(launch_reset(b->qctl_d, b->ring_d, b->qcap, b->order_d, b->stats_d, b->bad_d, b->npairs, s));
+    HIP_TRY(launch_reset(b->qctl_d, b->ring_d, b->qcap, b->order_d, b->stats_d, b->bad_d, b->npairs, s, b->hring_d));
     int prc = enqueue_pack(b, s);
     if (prc) return prc;
     HIP_TRY(launch_features(b->pplanes, b->tplanes, b->pword_d, b->tword_d, b->plen_d, b->tlen_d, b->npairs, b->p.W,

@@ -28,6 +28,10 @@ enum {
 
 constexpr int kMaxSlots = 16;     // windows in flight per wavefront
 constexpr int kSimdsPerCu = 4;    // SIMDs of a CDNA compute unit
+constexpr int kHelperSlots = 4;   // windows per wavefront of the off-track helper launch
+// queue-control words of the off-track helpers, 128 bytes apart (helpers poll them
+// while the main launch updates the first three)
+constexpr int kQcHHead = 32, kQcHTail = 64, kQcHInFlight = 96, kQcBeat = 128, kQcWords = 160;
 constexpr int kMaxClasses = 16;   // predictor classes
 constexpr int kMaxHidden = 64;
 constexpr int kFeatures = 16;
@@ -69,7 +73,10 @@ struct AlignArgs {
     // yields is appended at qctl[1] with its state saved in pstate.
     int32_t* ring;
     int64_t qcap;
-    uint32_t* qctl;               // [0] head, [1] tail, [2] pairs finished
+    uint32_t* qctl;               // [0] head, [1] tail, [2] pairs finished; with off-track
+                                  // helpers, each on a cache line of its own: head and tail of
+                                  // hring, pairs handed over and not finished, a beat of the
+                                  // main launch (kQcHHead.. below)
     int32_t* pstate;              // per pair: p0, t0, edits, nruns, cur_op, cur_len, next_w, 0
     int32_t yield_chars;          // a pair yields after advancing this many pattern chars (<= 0: never)
     unsigned long long* stats;    // ST_COUNT counters
@@ -81,11 +88,20 @@ struct AlignArgs {
     int32_t ring_rows;            // > 0: stored rows kept as a ring of this many slots (extended DENT)
     int32_t no_et;                // ablation: rows continue past d_w up to k_w
     int32_t one_per_simd;         // column blocks: the form that holds a whole SIMD per wavefront
+    // Off-track helpers (column blocks, plain mode).  The main launch hands a pair
+    // whose last mig_k windows all had d_w >= mig_d to hring (at most mig_cap such
+    // pairs unfinished at a time); a helper launch (helper = 1, fewer windows and
+    // more lanes per wavefront) takes pairs from hring only and resumes them.
+    int32_t* hring;               // npairs entries, pair + 1 once written
+    int32_t mig_k, mig_d, mig_cap;
+    int32_t helper;
+    int32_t idle_limit;           // helper: idle polls without a main-launch pass before it leaves
 };
 
 // launchers (defined in the .hip files)
 hipError_t launch_reset(uint32_t* qctl, int32_t* ring, int64_t qcap, const int32_t* order,
-                        unsigned long long* stats, uint8_t* bad, int32_t npairs, hipStream_t s);
+                        unsigned long long* stats, uint8_t* bad, int32_t npairs, hipStream_t s,
+                        int32_t* hring = nullptr);
 hipError_t launch_pack(const uint8_t* seq, const int64_t* off, const int64_t* wordoff, int32_t npairs,
                        int64_t total_words, int64_t total_bytes, Plane2* out, uint8_t* bad, int num_cu, hipStream_t s);
 hipError_t launch_align(const AlignArgs& a, int grid, size_t lds_bytes, hipStream_t s);

@@ -191,8 +191,71 @@ def test_one_wavefront_per_simd_refused_forms(ctx):
     from paper_2208_09985_amd import _lib as L, api
     b = synth.make_batch("small_100bp", 16)
     for kw in (dict(mode="learned"), dict(rows_lds=True), dict(store_edges=True), dict(row_ring=True),
-               dict(slots=16), dict(kernel="rows"), dict(kernel="lanes"), dict(W=96, O=24, k=96)):
+               dict(slots=32), dict(kernel="rows"), dict(kernel="lanes"), dict(W=96, O=24, k=96)):
         prm = dict(kernel="columns", one_per_simd=True)
+        prm.update(kw)
+        with pytest.raises(L.ScgError) as e:
+            api.Batch(ctx, b, api.params(**prm))
+        assert e.value.code == L.EINVAL, (kw, e.value)
+
+
+def _offtrack_batch(n_mixed=40, n_unrelated=12, seed=5):
+    # long pairs of which some lose the diagonal (unrelated sequences: every window deep)
+    mixed = synth.make_batch("mixed_10kbp", indices=range(500, 500 + n_mixed))
+    pats = [mixed.pat[mixed.pat_off[i]:mixed.pat_off[i + 1]].tobytes() for i in range(mixed.npairs)]
+    txts = [mixed.txt[mixed.txt_off[i]:mixed.txt_off[i + 1]].tobytes() for i in range(mixed.npairs)]
+    rng = np.random.default_rng(seed)
+    for i in range(n_unrelated):
+        p, t = synth.random_pair(rng, 1500 + 100 * i, 1500 + 100 * i)
+        pats.append(p)
+        txts.append(t)
+    return synth.from_lists(pats, txts)
+
+
+@pytest.mark.parametrize("W,O", [(64, 24), (64, 33), (32, 8)])
+def test_offtrack_helpers_keep_results(ctx, W, O):
+    # pairs handed to the 4-window helper launch after three deep windows come out
+    # exactly as the oracle's; the helper launch leaves once every pair is finished
+    from paper_2208_09985_amd import api
+    b = _offtrack_batch()
+    ref = oracle.align_batch(b, W, O, W)
+    bt = api.Batch(ctx, b, api.params(W=W, O=O, k=W, kernel="columns", offtrack_helpers=True))
+    shape = bt.launch_shape()
+    bt.close()
+    log(f"[parity] off-track helpers W={W} O={O} shape {shape}")
+    assert shape["helper_grid"] > 0 and shape["helper_slots"] == 4 and shape["slots"] == 16, shape
+    res = run_gpu(ctx, b, W=W, O=O, k=W, kernel="columns", offtrack_helpers=True)
+    compare(b, res, ref, f"off-track helpers W={W} O={O}")
+    assert res.stats.yields > 0, "no pair was handed over"
+
+
+def test_offtrack_helpers_idle_and_repeated(ctx):
+    # helpers that never receive a pair leave with the main launch; a prepared batch
+    # with helpers runs several times with the same results
+    import torch
+    from paper_2208_09985_amd import api
+    small = synth.make_batch("small_100bp", 600)
+    ref = oracle.align_batch(small, 64, 24, 64)
+    res = run_gpu(ctx, small, kernel="columns", offtrack_helpers=True)
+    compare(small, res, ref, "helpers idle")
+    assert res.stats.yields == 0
+    b = _offtrack_batch(24, 8, seed=9)
+    ref = oracle.align_batch(b, 64, 24, 64)
+    bt = api.Batch(ctx, b, api.params(kernel="columns", offtrack_helpers=True, slots=10))
+    for rep in range(3):
+        bt.edits.fill_(-7)
+        bt.run()
+        torch.cuda.synchronize()
+        compare(b, bt.result(), ref, f"helpers, run {rep}")
+    bt.close()
+
+
+def test_offtrack_helpers_refused_forms(ctx):
+    from paper_2208_09985_amd import _lib as L, api
+    b = synth.make_batch("small_100bp", 16)
+    for kw in (dict(mode="fixed", fixed_rows=7), dict(rows_lds=True), dict(store_edges=True), dict(graph=True),
+               dict(slots=4), dict(yield_chars=64), dict(one_per_simd=False), dict(kernel="rows")):
+        prm = dict(kernel="columns", offtrack_helpers=True)
         prm.update(kw)
         with pytest.raises(L.ScgError) as e:
             api.Batch(ctx, b, api.params(**prm))

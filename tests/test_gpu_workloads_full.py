@@ -66,9 +66,11 @@ def test_long_10kbp_all_pairs_plain_and_learned(ctx):
     shape = bt.launch_shape()
     log(f"[full] long_10kbp plain launch shape {shape}")
     if ctx.cus == 256:
-        # 1,250 wavefronts of 8 windows would not fit one per SIMD; 1,000 of 10 do
-        assert shape["kernel"] == "columns" and shape["slots"] == 10 and shape["one_per_simd"], shape
-        assert shape["grid"] == 1000 and shape["entry_bits"] == 48, shape
+        # 625 wavefronts of 16 windows, one per SIMD, and the off-track helper launch
+        # of 4-window wavefronts on the other 399 SIMDs
+        assert shape["kernel"] == "columns" and shape["slots"] == 16 and shape["one_per_simd"], shape
+        assert shape["grid"] == 625 and shape["entry_bits"] == 48, shape
+        assert shape["helper_grid"] == 399 and shape["helper_slots"] == 4, shape
     for rep in range(2):
         log(f"[full] long_10kbp plain, benchmark launch, run {rep}")
         bt.edits.fill_(-7)
@@ -79,10 +81,10 @@ def test_long_10kbp_all_pairs_plain_and_learned(ctx):
     st = bt.stats()
     bt.close()
     assert st.windows == ref["stats"].windows and st.ops_alg == ref["stats"].ops_alg
-    for slots, one in ((8, "auto"), (10, False), (16, "auto")):
-        log(f"[full] long_10kbp plain, {slots} windows per wavefront, one per SIMD: {one}")
-        compare(b, api.align_batch(ctx, b, kernel="columns", slots=slots, one_per_simd=one), ref,
-                f"long_10kbp full slots={slots} one_per_simd={one}")
+    for slots, one, helpers in ((8, "auto", "auto"), (10, "auto", False), (10, False, False), (16, "auto", False)):
+        log(f"[full] long_10kbp plain, {slots} windows per wavefront, one per SIMD: {one}, helpers: {helpers}")
+        compare(b, api.align_batch(ctx, b, kernel="columns", slots=slots, one_per_simd=one, offtrack_helpers=helpers),
+                ref, f"long_10kbp full slots={slots} one_per_simd={one} helpers={helpers}")
     for kw in (dict(rows_lds=True), dict(row_ring=True), dict(kernel="lanes")):
         log(f"[full] long_10kbp plain, {kw}")
         compare(b, api.align_batch(ctx, b, **{"kernel": "columns", **kw}), ref, f"long_10kbp full {kw}")
