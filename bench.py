@@ -328,13 +328,14 @@ def main():
         # lanes per window in the column-block kernel: 16, 8, 4 or 2 lanes (4, 8, 16 or 32 windows per
         # wavefront); the error-row lane kernel's plain figure is in `variants`
         # (10: six lanes of 12 columns), each with the automatic SIMD placement, and 8 and 10 also
-        # with wavefronts allowed to share a SIMD
+        # with wavefronts allowed to share a SIMD; none of them with the off-track helpers (the
+        # headline's launch is 16 windows per wavefront plus the helpers)
         lanes = {}
         for ng, one in ((4, "auto"), (8, "auto"), (8, False), (10, "auto"), (10, False), (16, "auto"), (32, "auto")):
             tag = f"windows_per_wavefront_{ng}" + ("_shared_simds" if one is False else "")
             lms_, lst_, _ = measure(batch, f"columns, {ng} windows per wavefront, one per SIMD {one}",
                                     api.params(W=w.W, O=w.O, k=w.k, mode="plain", kernel="columns", slots=ng,
-                                               one_per_simd=one), 5, 1)
+                                               one_per_simd=one, offtrack_helpers=False), 5, 1)
             e = summary(batch, lms_, lst_)
             e["lanes_per_window"] = 6 if ng == 10 else 64 // ng
             e["one_wavefront_per_simd"] = shapes[f"columns, {ng} windows per wavefront, one per SIMD {one}"]["one_per_simd"]
@@ -392,6 +393,9 @@ def main():
     shape = shapes["plain"]
     kname = (f"cols_kernel<false, {shape['slots']}, {stored_form(w.W - w.O)}, 0"
              + (", true>" if shape["one_per_simd"] else ">"))
+    if shape.get("helper_grid", 0) > 0:
+        # the off-track helper launch runs beside the main one; the kernel time spans both
+        kname += f" + cols_kernel<false, {shape['helper_slots']}, {stored_form(w.W - w.O)}, 0, true>"
     lanes_per_window = 64 // shape["slots"] if shape["slots"] != 10 else 6
     out = {
         "metric": METRIC,
@@ -419,10 +423,13 @@ def main():
                      "launch": shape,
                      "ops_alg_per_launch": int(st.ops_alg), "windows_per_launch": int(st.windows),
                      # lockstep: a pass of a wavefront runs as many row steps as its deepest
-                     # window needs; rows_needed is the mean of d_w + 1
-                     "lockstep": {"row_steps_per_window": round(st.lane_steps / 64 * shape["slots"] / max(st.windows, 1), 2),
+                     # window needs; rows_needed is the mean of d_w + 1 (row steps of both
+                     # launches when the off-track helpers run, each counted at its own width)
+                     "lockstep": {"row_steps_per_window": round(st.lane_steps / 64 * shape["slots"] / max(st.windows, 1), 2)
+                                  if not shape.get("helper_grid") else None,
                                   "rows_needed_per_window": round(st.rows_budgeted / max(st.windows, 1), 2),
-                                  "skew_steps": lanes_per_window - 1}},
+                                  "skew_steps": lanes_per_window - 1},
+                     "offtrack_pairs_handed_over": int(st.yields) if shape.get("helper_grid") else 0},
         "variants": variants,
         "workloads": workloads,
     }

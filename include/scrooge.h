@@ -152,11 +152,12 @@ typedef struct {
                             /* with 4 windows of 16 lanes each, on the SIMDs the main  */
                             /* launch (16 windows per wavefront, one per SIMD) leaves  */
                             /* free; its windows then take fewer instructions.  1 =    */
-                            /* always when the main launch fits, 0 = automatic (pairs  */
-                            /* longer than 32 windows on average, more pairs than      */
-                            /* 8-window wavefronts one per SIMD can hold, and 16-window */
-                            /* wavefronts that fit while leaving at least 128 SIMDs),  */
-                            /* -1 = never.  Results are the same either way            */
+                            /* always when the main launch fits, 0 = automatic (W-O at */
+                            /* least 30, pairs longer than 32 windows on average, more */
+                            /* pairs than 8-window wavefronts one per SIMD can hold,   */
+                            /* and 16-window wavefronts that fit while leaving at      */
+                            /* least 128 SIMDs), -1 = never.  Results are the same     */
+                            /* either way                                              */
 } scg_params;
 
 typedef struct {

@@ -690,7 +690,7 @@ int scg_batch_create(scg_ctx* c, const scg_params* params, int32_t npairs, const
             const bool long_pairs = npairs > 0 && total_m / npairs >= 32LL * (params->W - params->O);
             const bool fits = (mng == 8 || mng == 10 || mng == 16) && mwaves + 1 <= simds;
             const bool want = params->offtrack_helpers == 1 ||
-                              (long_pairs && waves(8) > simds && mwaves + 128 <= simds);
+                              (long_pairs && params->W - params->O >= 30 && waves(8) > simds && mwaves + 128 <= simds);
             if (ok && fits && want) {
                 b->ns = mng;
                 b->one = true;
