@@ -665,11 +665,18 @@ int scg_batch_create(scg_ctx* c, const scg_params* params, int32_t npairs, const
         const bool plain_global = params->mode == SCG_MODE_PLAIN &&
                                   !(params->flags & (SCG_FLAG_ROWS_LDS | SCG_FLAG_STORE_EDGES | SCG_FLAG_ROW_RING));
         auto waves = [&](int ng) { return ((int64_t)npairs + ng - 1) / ng; };
+        int64_t total_m = 0;
+        for (int32_t i = 0; i < npairs; ++i) total_m += pl[i];
+        // short reads (16 windows or fewer on average): their passes are short and
+        // the skew of many lanes per window dominates, so fewer lanes per window
+        // (16 windows per wavefront once those fill the SIMDs, else 8)
+        const bool short_reads = npairs > 0 && total_m <= 16LL * (params->W - params->O) * npairs;
         if (params->slots > 0)
             b->ns = params->slots <= 4 ? 4
                   : params->slots <= 8 ? 8
                   : (params->slots <= 10 && !learned) ? 10
                   : params->slots <= 16 ? 16 : 32;
+        else if (short_reads && params->mode == SCG_MODE_PLAIN) b->ns = waves(16) >= simds ? 16 : 8;
         else if (npairs < 8 * c->num_cu) b->ns = 4;
         else if (waves(8) > simds && waves(10) <= simds && plain_global && params->one_per_simd >= 0) b->ns = 10;
         else b->ns = 8;
@@ -685,8 +692,6 @@ int scg_batch_create(scg_ctx* c, const scg_params* params, int32_t npairs, const
                             params->one_per_simd >= 0 && params->offtrack_helpers >= 0;
             const int mng = params->slots > 0 ? b->ns : 16;
             const int64_t mwaves = waves(mng);
-            int64_t total_m = 0;
-            for (int32_t i = 0; i < npairs; ++i) total_m += pl[i];
             const bool long_pairs = npairs > 0 && total_m / npairs >= 32LL * (params->W - params->O);
             const bool fits = (mng == 8 || mng == 10 || mng == 16) && mwaves + 1 <= simds;
             const bool want = params->offtrack_helpers == 1 ||
