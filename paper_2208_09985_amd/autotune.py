@@ -5,7 +5,7 @@ For a given batch and mode it times candidate configurations on the device
 and keeps the fastest:
 
 * kernel        -- error-row lanes or column blocks
-* slots         -- windows in flight per wavefront
+* slots         -- windows in flight per wavefront (0: the library's automatic launch)
 * waves_per_cu  -- persistent wavefronts per CU (capped by LDS occupancy)
 * order         -- queue order of pairs (input order or longest first)
 * tau           -- learned mode: confidence needed before a smaller row budget
@@ -36,7 +36,7 @@ from . import api
 DEFAULT_CACHE = os.path.join(os.path.expanduser("~"), ".cache", "scrooge_mi355x", "autotune.json")
 
 SPACE = {
-    "plain": {"kernel": ["columns"], "slots": [4, 8, 10, 16], "waves_per_cu": [0], "order": ["input", "longest_first"],
+    "plain": {"kernel": ["columns"], "slots": [0, 4, 8, 10, 16], "waves_per_cu": [0], "order": ["input", "longest_first"],
               "rows_lds": [False, True], "one_per_simd": ["auto", False]},
     "fixed": {"kernel": ["rows"], "slots": [2, 4, 6, 8], "waves_per_cu": [0], "order": ["input"],
               "fixed_rows": [7, 11, 15, 23]},

@@ -72,6 +72,7 @@ struct scg_batch {
     uint64_t* dent_d = nullptr;     // column-block kernel: stored rows per group
     int dstride = 0;
     int lds_rows = 0;               // column-block kernel: stored rows kept in LDS
+    int chain_waves_per_cu = 0;     // column-block kernel: wavefronts per CU for uneven lengths (0: occupancy)
     int ring_rows = 0;              // column-block kernel: slots of the stored-row ring (0: 64 rows)
     bool cols = false;              // column-block kernel selected
     bool wide = false;              // windows of 65..128 characters (wide_kernel)
@@ -680,8 +681,33 @@ int scg_batch_create(scg_ctx* c, const scg_params* params, int32_t npairs, const
         else if (npairs < 8 * c->num_cu) b->ns = 4;
         else if (waves(8) > simds && waves(10) <= simds && plain_global && params->one_per_simd >= 0) b->ns = 10;
         else b->ns = 8;
+        // Lengths that vary, longest first: the longest pair's chain of windows sets the
+        // kernel's time once enough chains run beside it to cover the rest of the work,
+        // so a launch needs about (all windows / longest chain) windows in flight.  When
+        // that is fewer than the register-limited grid would hold, it runs 4-window
+        // wavefronts, just enough of them per CU, and the SIMDs they share are shared
+        // by fewer wavefronts.
+        if (params->slots == 0 && params->waves_per_cu == 0 && plain_global && longest_first && !short_reads &&
+            npairs >= 8 * c->num_cu && params->one_per_simd >= 0) {
+            const int64_t capw = params->W - params->O;
+            int64_t total_w = 0, max_w = 1;
+            for (int32_t i = 0; i < npairs; ++i) {
+                const int64_t w = (pl[i] + capw - 1) / capw;
+                total_w += w;
+                max_w = std::max(max_w, w);
+            }
+            const int64_t chains = (total_w + max_w - 1) / max_w;
+            const int64_t need_waves = (chains + 3) / 4;
+            const int occ = cols_max_blocks_per_cu(false, 4, 0, (int)capw, 0, false, false);
+            if (need_waves < (int64_t)occ * c->num_cu) {
+                b->ns = 4;
+                b->chain_waves_per_cu = (int)std::max<int64_t>(1, (need_waves + c->num_cu - 1) / c->num_cu);
+            }
+        }
         b->one = plain_global && (b->ns == 4 || b->ns == 8 || b->ns == 10 || b->ns == 16) &&
-                 (params->one_per_simd == 1 || (params->one_per_simd == 0 && waves(b->ns) <= simds));
+                 (params->one_per_simd == 1 ||
+                  (params->one_per_simd == 0 &&
+                   (waves(b->ns) <= simds || (b->chain_waves_per_cu > 0 && b->chain_waves_per_cu <= kSimdsPerCu))));
         // Off-track helpers.  A pair that has lost the diagonal keeps d_w near W-O in
         // every window, and such pairs set the kernel's time; a second launch of
         // 4-window wavefronts (16 lanes of 4 columns) on the SIMDs the main launch
@@ -699,6 +725,7 @@ int scg_batch_create(scg_ctx* c, const scg_params* params, int32_t npairs, const
             if (ok && fits && want) {
                 b->ns = mng;
                 b->one = true;
+                b->chain_waves_per_cu = 0;
                 b->help_grid = (int)std::min<int64_t>(simds - mwaves, ((int64_t)npairs + kHelperSlots - 1) / kHelperSlots);
                 b->mig_k = 3;
                 b->mig_d = std::max(1, (params->W - params->O) / 2);
@@ -741,6 +768,7 @@ int scg_batch_create(scg_ctx* c, const scg_params* params, int32_t npairs, const
         per_cu = align_max_blocks_per_cu(b->lds, learned);
     }
     if (params->waves_per_cu > 0) per_cu = std::min(per_cu, params->waves_per_cu);
+    if (b->chain_waves_per_cu > 0) per_cu = std::min(per_cu, b->chain_waves_per_cu);
     b->grid = std::max(1, per_cu * c->num_cu);
     const int64_t need = (npairs + b->ns - 1) / b->ns;   // more wavefronts than slots-worth of pairs idle
     if (b->grid > need) b->grid = (int)std::max<int64_t>(1, need);

@@ -5,8 +5,8 @@ operation stream (bit-exact).
 * short reads: 100,000 pairs of 250 bp, the default plain launch;
 * long reads: 10,000 pairs of 10 kbp, the default plain launch (the
   benchmark's headline) and, with the committed predictor, learned mode;
-* uneven lengths: 50,000 pairs of log-normal length, the launch shape the
-  autotuner picks, replayed from a captured hipGraph;
+* uneven lengths: 50,000 pairs of log-normal length, the default launch and
+  the launch shape the autotuner picks, replayed from a captured hipGraph;
 * mixed edit rates: 10,000 pairs of 10 kbp in learned mode with the
   committed predictor, in both kernels.
 """
@@ -96,6 +96,21 @@ def test_uneven_lognormal_all_pairs_autotuned_graph(ctx):
     import torch
     from paper_2208_09985_amd import api, autotune
     w, b, ref = _workload("uneven_lognormal")
+    # the default launch: lengths vary, so pairs go longest first, and the launch keeps
+    # about (all windows / longest chain of windows) in flight in 4-window wavefronts
+    bt = api.Batch(ctx, b, api.params(W=w.W, O=w.O, k=w.k, mode="plain"))
+    shape = bt.launch_shape()
+    log(f"[full] uneven_lognormal default launch shape {shape}")
+    m = np.diff(b.pat_off)
+    nwin = -(-m // (w.W - w.O))
+    chains = -(-int(nwin.sum()) // int(nwin.max()))
+    if ctx.cus == 256:
+        assert shape["kernel"] == "columns" and shape["slots"] == 4 and shape["helper_grid"] == 0, shape
+        assert shape["grid"] == 256 * -(-(-(-chains // 4)) // 256), (shape, chains)
+    bt.run()
+    torch.cuda.synchronize()
+    compare(b, bt.result(), ref, "uneven_lognormal full default launch")
+    bt.close()
     best, trials = autotune.tune(ctx, b, w.W, w.O, w.k, mode="plain", reps=1, cache_path=None, log=log)
     log(f"[full] uneven_lognormal autotuned {best}, graph launch")
     gb = api.Batch(ctx, b, api.params(W=w.W, O=w.O, k=w.k, mode="plain", graph=True, **best))
