@@ -127,8 +127,18 @@ typedef struct {
     int32_t slots;          /* windows in flight per wavefront, 1..16 (0 = automatic); */
                             /* column blocks round up to 4, 8, 16 or, in plain and     */
                             /* fixed modes, 10 (slots 9..10: six lanes of 12 columns)  */
-                            /* or 32 (slots 17..32)                                    */
-    int32_t waves_per_cu;   /* persistent wavefronts per CU (0 = occupancy maximum)    */
+                            /* or 32 (slots 17..32).  Automatic, column blocks: short  */
+                            /* reads (16 windows or fewer per pattern on average, plain */
+                            /* mode) 16 once those fill the SIMDs, else 8; fewer than  */
+                            /* 8 pairs per CU 4; lengths that vary, longest first      */
+                            /* (plain mode, rows in global memory) 4, with just enough */
+                            /* wavefronts per CU to keep (all windows / the longest    */
+                            /* pair's windows) windows in flight, when that is fewer   */
+                            /* than the occupancy maximum holds; otherwise 8 (10 when  */
+                            /* those fit one per SIMD and 8 do not); 16 with the       */
+                            /* off-track helpers                                       */
+    int32_t waves_per_cu;   /* persistent wavefronts per CU (0 = occupancy maximum, or */
+                            /* the count the automatic rule for varying lengths picks) */
     int32_t order;          /* SCG_ORDER_* : queue order of pairs                      */
     int32_t fixed_rows;     /* SCG_MODE_FIXED: rows computed before falling back       */
     float tau;              /* SCG_MODE_LEARNED: confidence needed for a smaller budget */
@@ -186,10 +196,10 @@ const char* scg_strerror(int code);
 const char* scg_last_hip_error(void);
 
 /* Default parameters: W=64, O=24, k=64, plain mode, automatic launch shape
- * (column blocks with 8 windows per wavefront in plain mode, 4 with fewer
- * than 8 pairs per CU; error-row lanes with 4 slots when windows start with
- * a row budget; the occupancy maximum of wavefronts per CU), fixed_rows = 15,
- * tau = 0.8, yield_chars = -1 (automatic). */
+ * (column blocks in plain mode, windows per wavefront as described at
+ * scg_params.slots; error-row lanes with 4 slots when windows start with a
+ * row budget), automatic queue order, one_per_simd and offtrack_helpers,
+ * fixed_rows = 15, tau = 0.8, yield_chars = -1 (automatic). */
 void scg_params_default(scg_params* p);
 
 /* Create a context on HIP device `device`.  *out receives the context; the
