@@ -99,6 +99,8 @@ enum {
                                         /* (as many as fit with the wavefronts the batch       */
                                         /* needs; 4, 8 or 16 windows per wavefront), the rest  */
                                         /* in global memory; by default all rows are global    */
+                                        /* in the main launch (the off-track helper launch     */
+                                        /* always keeps its lowest rows in LDS)                */
     SCG_FLAG_STORE_EDGES = 16,          /* store each entry's edge bitvectors (I, S, D of the  */
                                         /* row above and M, 32 bytes) instead of the entry (no */
                                         /* SENE); 4, 8 or 16 windows per wavefront, rows in    */
@@ -155,16 +157,18 @@ typedef struct {
                             /* the batch's wavefronts fit one per SIMD (10 windows per */
                             /* wavefront are then picked when 8 would not fit); -1 =   */
                             /* never.  Results are the same either way                 */
-    int32_t offtrack_helpers;  /* column blocks, plain mode, rows in global memory, no    */
-                            /* yields, ablations or graph: a pair whose last three     */
+    int32_t offtrack_helpers;  /* column blocks, plain mode, no yields, ablations or    */
+                            /* graph (SCG_FLAG_ROWS_LDS allowed, with 16 windows per   */
+                            /* main wavefront): a pair whose last three                */
                             /* windows each had d_w >= (W-O)/2 (it has lost the        */
                             /* diagonal) is handed to a second launch of wavefronts    */
                             /* with 4 windows of 16 lanes each, on the SIMDs the main  */
                             /* launch (16 windows per wavefront, one per SIMD) leaves  */
-                            /* free; its windows then take fewer instructions.  1 =    */
-                            /* always when the main launch fits, 0 = automatic (W-O at */
-                            /* least 30, pairs longer than 32 windows on average, more */
-                            /* pairs than 8-window wavefronts one per SIMD can hold,   */
+                            /* free, which keeps its windows' lowest rows in LDS; its  */
+                            /* windows then take fewer instructions.  1 = always when  */
+                            /* the main launch fits, 0 = automatic (W-O at least 30,   */
+                            /* pairs longer than 32 windows on average, at least as    */
+                            /* many pairs as 4-window wavefronts one per SIMD hold,    */
                             /* and 16-window wavefronts that fit while leaving at      */
                             /* least 128 SIMDs), -1 = never.  Results are the same     */
                             /* either way                                              */
@@ -252,7 +256,8 @@ int scg_batch_runs_offsets(const scg_batch* b, int64_t* out);
  * out[4] 1 for the form holding a whole SIMD per wavefront; out[5] stored
  * entry bits (32, 48 or 64; 96 or 128 for wide windows; 0 for error-row
  * lanes); out[6] wavefronts of the off-track helper launch (0: none);
- * out[7] its windows per wavefront.  out: 8 int32 in host memory.
+ * out[7] its windows per wavefront; out[8] its dynamic LDS bytes per
+ * wavefront.  out: 9 int32 in host memory.
  * Errors: SCG_EINVAL. */
 int scg_batch_launch_shape(const scg_batch* b, int32_t* out);
 

@@ -531,7 +531,44 @@ __global__ __launch_bounds__(64) void cols_kernel(const AlignArgs a) {
                     // 32- and 48-bit forms: the loaded words as they are (low planes of
                     // columns ti and ti+1; for 48 bits, their two high halves in one word)
                     uint32_t w0 = 0, w1 = 0, wh = 0;
-                    if constexpr (LR) {
+                    if constexpr (LR && (NARROW || SPLIT)) {
+                        // as the global form below, from LDS for rows below R (every lane
+                        // reads, at a clamped row) and from the global region under a
+                        // branch taken only when some group needs a deeper row; the global
+                        // words are consumed inside their branch
+                        struct __attribute__((packed, aligned(4))) W2 { uint2 v; };
+                        const uint32_t rr = (uint32_t)(max(td, 1) - 1);
+                        const uint32_t c0 = (uint32_t)min(ti, stride - 1), c1 = (uint32_t)min(ti + 1, stride - 1);
+                        const bool in_lds = rr < (uint32_t)R;
+                        const uint32_t rl = min(rr, (uint32_t)max(R, 1) - 1u);
+                        uint2 hv = uint2{0u, 0u};
+                        if (NARROW) {
+                            const uint32_t lo_row = lgbyte + rl * rowbytes;
+                            w0 = *reinterpret_cast<const uint32_t*>(lrows + (lo_row + c0 * 4u));
+                            w1 = *reinterpret_cast<const uint32_t*>(lrows + (lo_row + c1 * 4u));
+                        } else {
+                            const uint2 lv = reinterpret_cast<const W2*>(lrows + (lgbyte + rl * lobytes + c0 * 4u))->v;
+                            hv = reinterpret_cast<const W2*>(lrows + (lhiplane + rl * hibytes + (c0 & ~1u) * 2u))->v;
+                            w0 = lv.x;
+                            w1 = lv.y;
+                        }
+                        if (__ballot(!in_lds) != 0) {
+                            if (NARROW) {
+                                const uint32_t lo_row = gbyte + __umul24(rr, rowbytes);
+                                const uint32_t g0 = *reinterpret_cast<const uint32_t*>(bdent + (lo_row + c0 * 4u));
+                                const uint32_t g1 = *reinterpret_cast<const uint32_t*>(bdent + (lo_row + c1 * 4u));
+                                w0 = in_lds ? w0 : g0;
+                                w1 = in_lds ? w1 : g1;
+                            } else {
+                                const uint2 gl = reinterpret_cast<const W2*>(bdent + (gbyte + __umul24(rr, lobytes) + c0 * 4u))->v;
+                                const uint2 gh = reinterpret_cast<const W2*>(bdent + (hiplane + __umul24(rr, hibytes) + (c0 & ~1u) * 2u))->v;
+                                w0 = in_lds ? w0 : gl.x;
+                                w1 = in_lds ? w1 : gl.y;
+                                hv = in_lds ? hv : gh;
+                            }
+                        }
+                        if (SPLIT) wh = __builtin_amdgcn_alignbit(hv.y, hv.x, (c0 & 1u) * 16u);
+                    } else if constexpr (LR) {
                         const uint32_t rr = (uint32_t)(max(td, 1) - 1);
                         const uint32_t c0 = (uint32_t)min(ti, stride - 1), c1 = (uint32_t)min(ti + 1, stride - 1);
                         const bool in_lds = rr < (uint32_t)R;
@@ -632,7 +669,7 @@ __global__ __launch_bounds__(64) void cols_kernel(const AlignArgs a) {
                         sb = has_t & (int)((v1 >> (tj & 63)) & 1ull);
                         ib = (int)((v0 >> (tj & 63)) & 1ull);
                         db = has_t & (int)((tb_de >> (tj & 63)) & 1ull);
-                    } else if constexpr (!LR && (NARROW || SPLIT)) {
+                    } else if constexpr (NARROW || SPLIT) {
                         // W-O <= 47: an edit step has tj <= 46, so bits tj and tj+1 are stored
                         // bits and no implicit bit 64 is read.  Bits tj.. of each entry: a
                         // 32-bit entry shifted, or a 48-bit one funnel-shifted out of its high
@@ -811,7 +848,8 @@ static const void* cols_fn_plain(int ng, int sm) {
 // the one-wavefront-per-SIMD forms: plain mode, rows in global memory, 4, 8,
 // 10 or 16 windows per wavefront
 template <int ST>
-static const void* cols_fn_one(int ng) {
+static const void* cols_fn_one(int ng, int sm) {
+    if (sm == 1) return ng == 16 ? (const void*)cols_kernel<false, 16, ST, 1, true> : (const void*)cols_kernel<false, 4, ST, 1, true>;
     if (ng == 4) return (const void*)cols_kernel<false, 4, ST, 0, true>;
     if (ng == 8) return (const void*)cols_kernel<false, 8, ST, 0, true>;
     if (ng == 16) return (const void*)cols_kernel<false, 16, ST, 0, true>;
@@ -819,7 +857,7 @@ static const void* cols_fn_one(int ng) {
 }
 
 bool cols_one_per_simd_ok(bool learned, int ng, int sm, bool edges) {
-    return !learned && !edges && sm == 0 && (ng == 4 || ng == 8 || ng == 10 || ng == 16);
+    return !learned && !edges && ((sm == 0 && (ng == 4 || ng == 8 || ng == 10 || ng == 16)) || (sm == 1 && (ng == 4 || ng == 16)));
 }
 
 // the edge-storing ablation form: plain mode, 4, 8 or 16 windows per wavefront
@@ -838,7 +876,7 @@ int cols_max_blocks_per_cu(bool learned, int ng, size_t lds, int cap, int sm, bo
     int nb = 0;
     const int st = cols_store(learned, cap);
     if (one && !cols_one_per_simd_ok(learned, ng, sm, edges)) return 1;
-    const void* f = one ? (st == 1 ? cols_fn_one<1>(ng) : (st == 2 ? cols_fn_one<2>(ng) : cols_fn_one<0>(ng)))
+    const void* f = one ? (st == 1 ? cols_fn_one<1>(ng, sm) : (st == 2 ? cols_fn_one<2>(ng, sm) : cols_fn_one<0>(ng, sm)))
                   : learned ? cols_fn<true, 0>(ng)
                   : edges ? cols_fn_edges(ng, sm == 2 ? 2 : 0)
                   : (st == 1 ? cols_fn_plain<1>(ng, sm)
@@ -861,7 +899,9 @@ hipError_t launch_align_cols(const AlignArgs& a, int grid, int ng, size_t lds, h
     hipLaunchKernelGGL((cols_kernel<LRN, NGV, STV, LRV>), dim3(grid), dim3(64), lds, s, a)
 #define SCG_COLS_ONE(STV)                                                                          \
     do {                                                                                           \
-        if (ng == 4) hipLaunchKernelGGL((cols_kernel<false, 4, STV, 0, true>), dim3(grid), dim3(64), lds, s, a);       \
+        if (sm == 1 && ng == 16) hipLaunchKernelGGL((cols_kernel<false, 16, STV, 1, true>), dim3(grid), dim3(64), lds, s, a); \
+        else if (sm == 1) hipLaunchKernelGGL((cols_kernel<false, 4, STV, 1, true>), dim3(grid), dim3(64), lds, s, a);  \
+        else if (ng == 4) hipLaunchKernelGGL((cols_kernel<false, 4, STV, 0, true>), dim3(grid), dim3(64), lds, s, a);  \
         else if (ng == 8) hipLaunchKernelGGL((cols_kernel<false, 8, STV, 0, true>), dim3(grid), dim3(64), lds, s, a);  \
         else if (ng == 16) hipLaunchKernelGGL((cols_kernel<false, 16, STV, 0, true>), dim3(grid), dim3(64), lds, s, a); \
         else hipLaunchKernelGGL((cols_kernel<false, 10, STV, 0, true>), dim3(grid), dim3(64), lds, s, a);              \

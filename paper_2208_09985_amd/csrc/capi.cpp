@@ -73,6 +73,8 @@ struct scg_batch {
     int dstride = 0;
     int lds_rows = 0;               // column-block kernel: stored rows kept in LDS
     int chain_waves_per_cu = 0;     // column-block kernel: wavefronts per CU for uneven lengths (0: occupancy)
+    int help_lds_rows = 0;          // off-track helpers: stored rows kept in LDS, and the LDS bytes they take
+    size_t help_lds = 0;
     int ring_rows = 0;              // column-block kernel: slots of the stored-row ring (0: 64 rows)
     bool cols = false;              // column-block kernel selected
     bool wide = false;              // windows of 65..128 characters (wide_kernel)
@@ -165,12 +167,14 @@ int check_params(const scg_params* p) {
     // global memory, 4, 8 or 10 windows per wavefront
     if (p->one_per_simd < -1 || p->one_per_simd > 1) return SCG_EINVAL;
     if (p->offtrack_helpers < -1 || p->offtrack_helpers > 1) return SCG_EINVAL;
-    // off-track helpers forced: plain mode in the column-block kernel, rows in global
-    // memory, no yields, ablations or graph, 8, 10 or 16 windows per main wavefront
+    // off-track helpers forced: plain mode in the column-block kernel, no yields,
+    // ablations or graph, 8, 10 or 16 windows per main wavefront (16 when the main
+    // launch keeps rows in LDS)
     if (p->offtrack_helpers == 1 &&
         (p->mode != SCG_MODE_PLAIN || p->W > 64 || p->kernel == SCG_KERNEL_ROWS || p->kernel == SCG_KERNEL_LANES ||
-         p->flags != 0 || p->yield_chars > 0 || p->one_per_simd < 0 ||
-         (p->slots != 0 && p->slots != 8 && p->slots != 10 && p->slots != 16)))
+         (p->flags & ~SCG_FLAG_ROWS_LDS) != 0 || p->yield_chars > 0 || p->one_per_simd < 0 ||
+         (p->slots != 0 && p->slots != 8 && p->slots != 10 && p->slots != 16) ||
+         ((p->flags & SCG_FLAG_ROWS_LDS) && p->slots != 0 && p->slots != 16)))
         return SCG_EINVAL;
     if (p->one_per_simd == 1 &&
         (p->mode != SCG_MODE_PLAIN || p->W > 64 || p->kernel == SCG_KERNEL_ROWS || p->kernel == SCG_KERNEL_LANES ||
@@ -298,7 +302,8 @@ int enqueue_run(scg_batch* b, hipStream_t s, int32_t* edits, int32_t* text_end, 
             h.ns = kHelperSlots;
             h.dent = b->help_dent_d;
             h.dstride = cols_dent_stride(a.cap, kHelperSlots);
-            HIP_TRY(launch_align_cols(h, b->help_grid, kHelperSlots, 0, b->s2));
+            h.lds_rows = b->help_lds_rows;
+            HIP_TRY(launch_align_cols(h, b->help_grid, kHelperSlots, b->help_lds, b->s2));
             HIP_TRY(hipEventRecord(b->join_ev, b->s2));
             HIP_TRY(hipStreamWaitEvent(s, b->join_ev, 0));
         } else if (b->cols) HIP_TRY(launch_align_cols(a, b->grid, b->ns, b->lds, s));
@@ -714,14 +719,15 @@ int scg_batch_create(scg_ctx* c, const scg_params* params, int32_t npairs, const
         // leaves free takes them over.  The main launch then runs 16 windows per
         // wavefront (unless slots says otherwise), one wavefront per SIMD.
         {
-            const bool ok = params->mode == SCG_MODE_PLAIN && params->flags == 0 && params->yield_chars <= 0 &&
-                            params->one_per_simd >= 0 && params->offtrack_helpers >= 0;
+            const bool rows_lds = (params->flags & SCG_FLAG_ROWS_LDS) != 0;
+            const bool ok = params->mode == SCG_MODE_PLAIN && (params->flags & ~SCG_FLAG_ROWS_LDS) == 0 &&
+                            params->yield_chars <= 0 && params->one_per_simd >= 0 && params->offtrack_helpers >= 0;
             const int mng = params->slots > 0 ? b->ns : 16;
             const int64_t mwaves = waves(mng);
             const bool long_pairs = npairs > 0 && total_m / npairs >= 32LL * (params->W - params->O);
-            const bool fits = (mng == 8 || mng == 10 || mng == 16) && mwaves + 1 <= simds;
+            const bool fits = (mng == 8 || mng == 10 || mng == 16) && (!rows_lds || mng == 16) && mwaves + 1 <= simds;
             const bool want = params->offtrack_helpers == 1 ||
-                              (long_pairs && params->W - params->O >= 30 && waves(8) > simds && mwaves + 128 <= simds);
+                              (long_pairs && params->W - params->O >= 30 && waves(4) >= simds && mwaves + 128 <= simds);
             if (ok && fits && want) {
                 b->ns = mng;
                 b->one = true;
@@ -730,6 +736,16 @@ int scg_batch_create(scg_ctx* c, const scg_params* params, int32_t npairs, const
                 b->mig_k = 3;
                 b->mig_d = std::max(1, (params->W - params->O) / 2);
                 b->mig_cap = b->help_grid * kHelperSlots;
+                // the helpers keep the lowest stored rows of their windows in LDS (deep
+                // windows: nearly all of them); one wavefront per SIMD leaves each a
+                // quarter of the CU's LDS
+                const int hcap = params->W - params->O;
+                const size_t rowb = (size_t)kHelperSlots * cols_lds_row_bytes(false, hcap, cols_dent_stride(hcap, kHelperSlots));
+                const size_t budget = std::min(c->lds_per_cu / (size_t)kSimdsPerCu, c->lds_per_block);
+                const size_t reserve = 2048;   // the kernel's own shared records
+                const int rows = budget > reserve ? (int)((budget - reserve) / rowb) : 0;
+                b->help_lds_rows = std::min(rows, 64);
+                b->help_lds = (size_t)b->help_lds_rows * rowb;
             }
         }
         // SCG_FLAG_ROWS_LDS: the lowest stored rows of each window in LDS, as
@@ -753,7 +769,9 @@ int scg_batch_create(scg_ctx* c, const scg_params* params, int32_t npairs, const
             int vg = cols_max_blocks_per_cu(learned, b->ns, 0, cap, 1, false);
             if (params->waves_per_cu > 0) vg = std::min(vg, params->waves_per_cu);
             const int64_t waves = (npairs + b->ns - 1) / b->ns;
-            const int resident = (int)std::max<int64_t>(1, std::min<int64_t>(vg, (waves + c->num_cu - 1) / c->num_cu));
+            // one wavefront per SIMD (with the off-track helpers, which take the same share)
+            const int resident = b->one ? kSimdsPerCu
+                                        : (int)std::max<int64_t>(1, std::min<int64_t>(vg, (waves + c->num_cu - 1) / c->num_cu));
             const size_t budget = std::min(c->lds_per_cu / (size_t)resident, c->lds_per_block);
             const size_t reserve = 2048;   // the kernel's own shared records
             const int rows = budget > reserve ? (int)((budget - reserve) / rowb) : 0;
@@ -821,6 +839,7 @@ int scg_batch_launch_shape(const scg_batch* b, int32_t* out) {
     out[4] = b->one ? 1 : 0;
     out[6] = b->help_grid;
     out[7] = b->help_grid > 0 ? kHelperSlots : 0;
+    out[8] = b->help_grid > 0 ? (int32_t)b->help_lds : 0;
     if (b->wide) out[5] = cap <= 95 ? 96 : 128;
     else if (b->cols) out[5] = (b->p.flags & SCG_FLAG_STORE_EDGES) || learned ? 64 : (cap <= 31 ? 32 : (cap <= 47 ? 48 : 64));
     else if (b->lanes) out[5] = 64;

@@ -212,20 +212,24 @@ def _offtrack_batch(n_mixed=40, n_unrelated=12, seed=5):
     return synth.from_lists(pats, txts)
 
 
-@pytest.mark.parametrize("W,O", [(64, 24), (64, 33), (32, 8)])
-def test_offtrack_helpers_keep_results(ctx, W, O):
+@pytest.mark.parametrize("W,O,rows_lds", [(64, 24, False), (64, 33, False), (32, 8, False), (64, 16, False),
+                                           (64, 17, False), (64, 24, True), (64, 16, True)])
+def test_offtrack_helpers_keep_results(ctx, W, O, rows_lds):
     # pairs handed to the 4-window helper launch after three deep windows come out
-    # exactly as the oracle's; the helper launch leaves once every pair is finished
+    # exactly as the oracle's; the helper launch leaves once every pair is finished.
+    # The helpers keep their lowest rows in LDS (32-, 48- and 64-bit entries: W-O of
+    # 31, 40 and 47, and 48); with rows_lds the main launch does too
     from paper_2208_09985_amd import api
     b = _offtrack_batch()
     ref = oracle.align_batch(b, W, O, W)
-    bt = api.Batch(ctx, b, api.params(W=W, O=O, k=W, kernel="columns", offtrack_helpers=True))
+    bt = api.Batch(ctx, b, api.params(W=W, O=O, k=W, kernel="columns", offtrack_helpers=True, rows_lds=rows_lds))
     shape = bt.launch_shape()
     bt.close()
-    log(f"[parity] off-track helpers W={W} O={O} shape {shape}")
+    log(f"[parity] off-track helpers W={W} O={O} rows_lds={rows_lds} shape {shape}")
     assert shape["helper_grid"] > 0 and shape["helper_slots"] == 4 and shape["slots"] == 16, shape
-    res = run_gpu(ctx, b, W=W, O=O, k=W, kernel="columns", offtrack_helpers=True)
-    compare(b, res, ref, f"off-track helpers W={W} O={O}")
+    assert (shape["lds_bytes"] > 0) == rows_lds and shape["helper_lds_bytes"] > 0, shape
+    res = run_gpu(ctx, b, W=W, O=O, k=W, kernel="columns", offtrack_helpers=True, rows_lds=rows_lds)
+    compare(b, res, ref, f"off-track helpers W={W} O={O} rows_lds={rows_lds}")
     assert res.stats.yields > 0, "no pair was handed over"
 
 
@@ -253,7 +257,7 @@ def test_offtrack_helpers_idle_and_repeated(ctx):
 def test_offtrack_helpers_refused_forms(ctx):
     from paper_2208_09985_amd import _lib as L, api
     b = synth.make_batch("small_100bp", 16)
-    for kw in (dict(mode="fixed", fixed_rows=7), dict(rows_lds=True), dict(store_edges=True), dict(graph=True),
+    for kw in (dict(mode="fixed", fixed_rows=7), dict(rows_lds=True, slots=10), dict(store_edges=True), dict(graph=True),
                dict(slots=4), dict(yield_chars=64), dict(one_per_simd=False), dict(kernel="rows")):
         prm = dict(kernel="columns", offtrack_helpers=True)
         prm.update(kw)

@@ -67,10 +67,10 @@ def test_long_10kbp_all_pairs_plain_and_learned(ctx):
     log(f"[full] long_10kbp plain launch shape {shape}")
     if ctx.cus == 256:
         # 625 wavefronts of 16 windows, one per SIMD, and the off-track helper launch
-        # of 4-window wavefronts on the other 399 SIMDs
+        # of 4-window wavefronts on the other 399 SIMDs, their rows in LDS
         assert shape["kernel"] == "columns" and shape["slots"] == 16 and shape["one_per_simd"], shape
         assert shape["grid"] == 625 and shape["entry_bits"] == 48, shape
-        assert shape["helper_grid"] == 399 and shape["helper_slots"] == 4, shape
+        assert shape["helper_grid"] == 399 and shape["helper_slots"] == 4 and shape["helper_lds_bytes"] > 0, shape
     for rep in range(2):
         log(f"[full] long_10kbp plain, benchmark launch, run {rep}")
         bt.edits.fill_(-7)
