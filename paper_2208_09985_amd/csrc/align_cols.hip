@@ -330,8 +330,11 @@ __global__ __launch_bounds__(64) void cols_kernel(const AlignArgs a) {
             if (a.helper) {
                 // a helper waits for handed-over pairs while the main launch runs: its
                 // slots poll their own hring entries; the shared counters are read once
-                // every 16 sleeps, and it leaves after idle_limit such reads in which the
-                // main launch showed no beat
+                // every 16 sleeps.  After idle_limit such reads in which the main launch
+                // showed no beat (it has not started, or has ended) the helper closes the
+                // hand-over gate, so no pair can be handed over later, and leaves once
+                // every pair handed over before that is finished (until then a slot
+                // that holds a reserved hring entry may still receive one)
                 idle += 1u;
                 if ((idle & 15u) != 0u) {
                     __builtin_amdgcn_s_sleep(32);
@@ -344,7 +347,10 @@ __global__ __launch_bounds__(64) void cols_kernel(const AlignArgs a) {
                     beat = b;
                     idle = 0u;
                 } else if ((idle >> 4) > (uint32_t)a.idle_limit) {
-                    break;
+                    uint32_t v = 0u;
+                    if (lane == 0) v = atomicOr(&a.qctl[kQcHInFlight], kQcGateClosed);
+                    v = __builtin_amdgcn_readfirstlane(v);
+                    if ((v & ~kQcGateClosed) == 0u) break;
                 }
                 __builtin_amdgcn_s_sleep(32);
                 continue;
@@ -738,7 +744,9 @@ __global__ __launch_bounds__(64) void cols_kernel(const AlignArgs a) {
                     if (a.helper) atomicSub(&a.qctl[kQcHInFlight], 1u);
                 } else if (a.mig_k > 0 && deep_run >= a.mig_k) {
                     // off track: hand the pair to the helper launch, which gives a window
-                    // more lanes (each pair moves at most once, so hring never overflows)
+                    // more lanes (each pair moves at most once, so hring never overflows).
+                    // The in-flight word reserves a helper slot; once a helper has closed
+                    // the gate it exceeds the cap and the pair stays here
                     if (atomicAdd(&a.qctl[kQcHInFlight], 1u) < (uint32_t)a.mig_cap) {
                         const uint32_t tq = atomicAdd(&a.qctl[kQcHTail], 1u);
                         int32_t* st = a.pstate + 8 * (int64_t)pair;

@@ -9,6 +9,7 @@
 #include <algorithm>
 #include <cmath>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <new>
 #include <numeric>
@@ -75,6 +76,10 @@ struct scg_batch {
     int chain_waves_per_cu = 0;     // column-block kernel: wavefronts per CU for uneven lengths (0: occupancy)
     int help_lds_rows = 0;          // off-track helpers: stored rows kept in LDS, and the LDS bytes they take
     size_t help_lds = 0;
+    // off-track helpers: idle polls (each 16 sleeps of 32 x 64 cycles) without a beat of the
+    // main launch before a helper stops waiting; 4096 is some 55 ms.  The environment
+    // variable SCG_HELPER_IDLE_POLLS (a count >= 0) replaces it when the batch is created
+    int idle_limit = 1 << 12;
     int ring_rows = 0;              // column-block kernel: slots of the stored-row ring (0: 64 rows)
     bool cols = false;              // column-block kernel selected
     bool wide = false;              // windows of 65..128 characters (wide_kernel)
@@ -286,7 +291,7 @@ int enqueue_run(scg_batch* b, hipStream_t s, int32_t* edits, int32_t* text_end, 
     a.mig_d = b->mig_d;
     a.mig_cap = b->mig_cap;
     a.helper = 0;
-    a.idle_limit = 1 << 12;   // about 4096 x 16 sleeps of 32 x 64 cycles: some 55 ms with no main beat
+    a.idle_limit = b->idle_limit;
     if (b->npairs > 0) {
         if (b->lanes) HIP_TRY(launch_align_lane(a, b->grid, s));
         else if (b->wide) HIP_TRY(launch_align_wide(a, b->grid, b->ns, s));
@@ -736,6 +741,11 @@ int scg_batch_create(scg_ctx* c, const scg_params* params, int32_t npairs, const
                 b->mig_k = 3;
                 b->mig_d = std::max(1, (params->W - params->O) / 2);
                 b->mig_cap = b->help_grid * kHelperSlots;
+                if (const char* e = std::getenv("SCG_HELPER_IDLE_POLLS")) {
+                    char* end = nullptr;
+                    const long v = std::strtol(e, &end, 10);
+                    if (end != e && *end == '\0' && v >= 0 && v <= (1L << 24)) b->idle_limit = (int)v;
+                }
                 // the helpers keep the lowest stored rows of their windows in LDS (deep
                 // windows: nearly all of them); one wavefront per SIMD leaves each a
                 // quarter of the CU's LDS

@@ -32,6 +32,9 @@ constexpr int kHelperSlots = 4;   // windows per wavefront of the off-track help
 // queue-control words of the off-track helpers, 128 bytes apart (helpers poll them
 // while the main launch updates the first three)
 constexpr int kQcHHead = 32, kQcHTail = 64, kQcHInFlight = 96, kQcBeat = 128, kQcWords = 160;
+// set in the in-flight word by a helper that stops waiting: every later hand-over
+// then fails (the word exceeds any cap) and the main launch keeps its pairs
+constexpr uint32_t kQcGateClosed = 0x80000000u;
 constexpr int kMaxClasses = 16;   // predictor classes
 constexpr int kMaxHidden = 64;
 constexpr int kFeatures = 16;
@@ -95,7 +98,9 @@ struct AlignArgs {
     int32_t* hring;               // npairs entries, pair + 1 once written
     int32_t mig_k, mig_d, mig_cap;
     int32_t helper;
-    int32_t idle_limit;           // helper: idle polls without a main-launch pass before it leaves
+    int32_t idle_limit;           // helper: idle polls without a main-launch pass before it stops
+                                  // waiting (closes the hand-over gate and leaves once every pair
+                                  // handed over so far is finished)
 };
 
 // launchers (defined in the .hip files)

@@ -254,6 +254,23 @@ def test_offtrack_helpers_idle_and_repeated(ctx):
     bt.close()
 
 
+def test_offtrack_helpers_stop_waiting(ctx, monkeypatch):
+    # a helper that sees no beat of the main launch for idle_limit polls (forced small
+    # from the host) closes the hand-over gate: pairs handed over before that are
+    # still finished by the helpers, later ones stay in the main launch, and the
+    # results are the oracle's either way
+    from paper_2208_09985_amd import api
+    b = _offtrack_batch(24, 8, seed=11)
+    ref = oracle.align_batch(b, 64, 24, 64)
+    for polls in ("0", "1", "3", "40"):
+        monkeypatch.setenv("SCG_HELPER_IDLE_POLLS", polls)
+        log(f"[parity] helpers stop waiting after {polls} idle polls")
+        res = run_gpu(ctx, b, kernel="columns", offtrack_helpers=True)
+        compare(b, res, ref, f"helpers stop waiting after {polls} polls")
+        log(f"[parity]   pairs handed over: {res.stats.yields}")
+    monkeypatch.delenv("SCG_HELPER_IDLE_POLLS")
+
+
 def test_offtrack_helpers_refused_forms(ctx):
     from paper_2208_09985_amd import _lib as L, api
     b = synth.make_batch("small_100bp", 16)
