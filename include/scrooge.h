@@ -160,7 +160,7 @@ typedef struct {
     int32_t offtrack_helpers;  /* column blocks, plain mode, no yields, ablations or    */
                             /* graph (SCG_FLAG_ROWS_LDS allowed, with 16 windows per   */
                             /* main wavefront): a pair whose last three                */
-                            /* windows each had d_w >= (W-O)/2 (it has lost the        */
+                            /* windows each had d_w >= 3(W-O)/5 (it has lost the      */
                             /* diagonal) is handed to a second launch of wavefronts    */
                             /* with 4 windows of 16 lanes each, on the SIMDs the main  */
                             /* launch (16 windows per wavefront, one per SIMD) leaves  */

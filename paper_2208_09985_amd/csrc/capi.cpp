@@ -739,7 +739,7 @@ int scg_batch_create(scg_ctx* c, const scg_params* params, int32_t npairs, const
                 b->chain_waves_per_cu = 0;
                 b->help_grid = (int)std::min<int64_t>(simds - mwaves, ((int64_t)npairs + kHelperSlots - 1) / kHelperSlots);
                 b->mig_k = 3;
-                b->mig_d = std::max(1, (params->W - params->O) / 2);
+                b->mig_d = std::max(1, 3 * (params->W - params->O) / 5);
                 b->mig_cap = b->help_grid * kHelperSlots;
                 if (const char* e = std::getenv("SCG_HELPER_IDLE_POLLS")) {
                     char* end = nullptr;
