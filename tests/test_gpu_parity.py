@@ -74,6 +74,24 @@ def test_uneven_and_mixed_samples(ctx):
     check(ctx, synth.make_batch("mixed_10kbp", 32), mode="fixed", fixed_rows=8, what="mixed_10kbp fixed8")
 
 
+def test_uneven_chain_launch_one_per_simd(ctx):
+    # 3,000 pairs of log-normal length: longest first, and the automatic launch keeps
+    # about (all windows / longest chain) windows in flight, here one 4-window
+    # wavefront per CU and per SIMD at most
+    from paper_2208_09985_amd import api
+    b = synth.make_batch("uneven_lognormal", 3000)
+    ref = oracle.align_batch(b, 64, 24, 64)
+    bt = api.Batch(ctx, b, api.params())
+    shape = bt.launch_shape()
+    bt.close()
+    log(f"[parity] uneven 3,000 pairs, default launch shape {shape}")
+    if ctx.cus == 256:
+        assert shape["kernel"] == "columns" and shape["slots"] == 4 and shape["one_per_simd"], shape
+        assert shape["grid"] == 256 and shape["helper_grid"] == 0, shape
+    res = run_gpu(ctx, b)
+    compare(b, res, ref, "uneven 3,000 pairs, chain launch")
+
+
 @pytest.mark.parametrize("W,O,k", [(64, 33, 64), (32, 17, 32), (16, 9, 16), (8, 3, 8), (4, 3, 4), (64, 0, 64),
                                    (64, 63, 64), (1, 0, 1), (48, 20, 30), (64, 24, 6), (64, 17, 64), (64, 16, 64)])
 def test_window_parameters(ctx, W, O, k):
