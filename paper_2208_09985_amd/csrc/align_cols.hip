@@ -161,6 +161,12 @@ __global__ __launch_bounds__(64) void cols_kernel(const AlignArgs a) {
     int64_t roff = 0, rcap = 0, pending = -1;
     int polled = 0;
     int deep_run = 0;   // slot lane: consecutive windows of the pair with d_w >= mig_d
+    // slot lane, one-per-SIMD form: planes words cpq..cpq+2 of the pair's pattern and
+    // ctq..ctq+2 of its text (pair cpair)
+    Plane2 cpw0{0, 0}, cpw1{0, 0}, cpw2{0, 0}, ctw0{0, 0}, ctw1{0, 0}, ctw2{0, 0};
+    int cpair = -1, cpq = 0, ctq = 0;
+    const Plane2* cpb = a.pplanes;
+    const Plane2* ctb = a.tplanes;
     bool exhausted = !slot;
     // the queue this launch takes pairs from: the main ring, or (helper) hring
     uint32_t* const qhead = a.helper ? &a.qctl[kQcHHead] : &a.qctl[0];
@@ -233,8 +239,49 @@ __global__ __launch_bounds__(64) void cols_kernel(const AlignArgs a) {
                 kw = min(a.k, mw);
                 const int rows_full = (kw == mw) ? mw : kw + 1;   // row m_w is implicit: D(0,0) <= m_w
                 uint64_t plo, phi, tlo = 0, thi = 0;
-                load_window(a.pplanes + a.pword[pair], p0, plo, phi);
-                if (nw > 0) load_window(a.tplanes + a.tword[pair], t0, tlo, thi);
+                if constexpr (OW) {
+                    // the slot keeps planes words q and q+1 of both sequences from the window's
+                    // start q, and word q+2, loaded a whole pass before it is read: the next
+                    // window starts at most 63 characters further, in word q or q+1 (a reload
+                    // only for a new or moved pair).  One load site per sequence, so that the
+                    // loaded registers are the kept ones and nothing waits for them here
+                    const int pq = p0 >> 6, tq = t0 >> 6;
+                    const int plast = (m + 63) >> 6, tlast = (n + 63) >> 6;   // the sequence's last (padding) word
+                    if (pair != cpair || pq < cpq || pq > cpq + 1 || tq < ctq || tq > ctq + 1) {
+                        cpb = a.pplanes + a.pword[pair];
+                        ctb = a.tplanes + a.tword[pair];
+                        cpair = pair;
+                        cpq = pq;
+                        ctq = tq;
+                        cpw0 = cpb[pq];
+                        cpw1 = cpb[pq + 1];
+                        ctw0 = ctb[min(tq, tlast)];
+                        ctw1 = ctb[min(tq + 1, tlast)];
+                    } else {
+                        if (pq == cpq + 1) {
+                            cpw0 = cpw1;
+                            cpw1 = cpw2;
+                            cpq = pq;
+                        }
+                        if (tq == ctq + 1) {
+                            ctw0 = ctw1;
+                            ctw1 = ctw2;
+                            ctq = tq;
+                        }
+                    }
+                    cpw2 = cpb[min(cpq + 2, plast)];
+                    ctw2 = ctb[min(ctq + 2, tlast)];
+                    const uint32_t pr = (uint32_t)(p0 & 63), tr = (uint32_t)(t0 & 63);
+                    plo = pr ? (cpw0.lo >> pr) | (cpw1.lo << (64u - pr)) : cpw0.lo;
+                    phi = pr ? (cpw0.hi >> pr) | (cpw1.hi << (64u - pr)) : cpw0.hi;
+                    if (nw > 0) {
+                        tlo = tr ? (ctw0.lo >> tr) | (ctw1.lo << (64u - tr)) : ctw0.lo;
+                        thi = tr ? (ctw0.hi >> tr) | (ctw1.hi << (64u - tr)) : ctw0.hi;
+                    }
+                } else {
+                    load_window(a.pplanes + a.pword[pair], p0, plo, phi);
+                    if (nw > 0) load_window(a.tplanes + a.tword[pair], t0, tlo, thi);
+                }
                 r.plo = plo;
                 r.phi = phi;
                 r.tlo = tlo;
