@@ -344,13 +344,21 @@ __global__ __launch_bounds__(64) void cols_kernel(const AlignArgs a) {
                 const uint32_t tql = CB * q < 64 ? (uint32_t)(r.tlo >> (CB * q)) : 0u;
                 const uint32_t tqh = CB * q < 64 ? (uint32_t)(r.thi >> (CB * q)) : 0u;
                 const int ncols = min(max(r.n_w - CB * q, 0), CB);   // this lane's columns inside the text window
+                // match mask of column t: the pattern positions whose base equals text base t,
+                // i.e. plane bits equal to the text bit's in both planes: with m = 0 or ~0 the
+                // text bit, ~((p_lo ^ m_lo) | (p_hi ^ m_hi)); zero past the text window's end,
+                // and set beyond m_w.  Per 32-bit half, one-bit fields sign-extended to masks
+                const uint32_t vmask = ncols >= 32 ? ~0u : (1u << ncols) - 1u;   // ncols <= CB <= 32
+                const uint32_t pl0 = (uint32_t)r.plo, pl1 = (uint32_t)(r.plo >> 32);
+                const uint32_t ph0 = (uint32_t)r.phi, ph1 = (uint32_t)(r.phi >> 32);
+                const uint32_t by0 = (uint32_t)beyond, by1 = (uint32_t)(beyond >> 32);
 #pragma unroll
                 for (int t = 0; t < CB; ++t) {
-                    const uint64_t sl = ((tql >> t) & 1u) ? r.plo : ~r.plo;
-                    const uint64_t sh = ((tqh >> t) & 1u) ? r.phi : ~r.phi;
-                    const uint64_t e = (t < ncols ? (sl & sh) : 0ull) | beyond;
-                    E.lo[t] = (uint32_t)e;
-                    E.hi[t] = (uint32_t)(e >> 32);
+                    const uint32_t ml = (uint32_t)__builtin_amdgcn_sbfe((int)tql, (uint32_t)t, 1u);
+                    const uint32_t mh = (uint32_t)__builtin_amdgcn_sbfe((int)tqh, (uint32_t)t, 1u);
+                    const uint32_t vm = (uint32_t)__builtin_amdgcn_sbfe((int)vmask, (uint32_t)t, 1u);
+                    E.lo[t] = (~((pl0 ^ ml) | (ph0 ^ mh)) & vm) | by0;
+                    E.hi[t] = (~((pl1 ^ ml) | (ph1 ^ mh)) & vm) | by1;
                     A.lo[t] = 0;
                     A.hi[t] = 0;
                 }
