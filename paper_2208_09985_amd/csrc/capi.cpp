@@ -747,13 +747,14 @@ int scg_batch_create(scg_ctx* c, const scg_params* params, int32_t npairs, const
                     if (end != e && *end == '\0' && v >= 0 && v <= (1L << 24)) b->idle_limit = (int)v;
                 }
                 // the helpers keep the lowest stored rows of their windows in LDS (deep
-                // windows: nearly all of them).  The main launch uses no LDS, and a CU holds
-                // at most two helper wavefronts (it keeps at least two SIMDs for the main
-                // launch's 16-window wavefronts when these fill more than half the SIMDs), so
-                // each may take half of the CU's LDS
+                // windows: nearly all of them).  When the main launch keeps its rows in
+                // global memory it uses no LDS, and when its 16-window wavefronts fill more
+                // than half the SIMDs a CU holds at most two helper wavefronts, so each may
+                // take half of the CU's LDS; otherwise a quarter (one wavefront per SIMD)
                 const int hcap = params->W - params->O;
                 const size_t rowb = (size_t)kHelperSlots * cols_lds_row_bytes(false, hcap, cols_dent_stride(hcap, kHelperSlots));
-                const size_t budget = std::min(c->lds_per_cu / (size_t)(2 * mwaves >= simds ? 2 : kSimdsPerCu), c->lds_per_block);
+                const bool half = !rows_lds && 2 * mwaves >= simds;
+                const size_t budget = std::min(c->lds_per_cu / (size_t)(half ? 2 : kSimdsPerCu), c->lds_per_block);
                 const size_t reserve = 2048;   // the kernel's own shared records
                 const int rows = budget > reserve ? (int)((budget - reserve) / rowb) : 0;
                 b->help_lds_rows = std::min(rows, 64);
