@@ -496,7 +496,11 @@ __global__ __launch_bounds__(64) void cols_kernel(const AlignArgs a) {
                         }
                     };
                     const uint32_t udh = (uint32_t)dh;
-                    if (LR && udh < (uint32_t)R) {
+                    if (LR && R >= kStoredRows) {
+                        // every stored row in LDS (a wavefront-uniform test, so no divergent branch)
+                        put(lrows, lgbyte + udh * (SPLIT ? lobytes : rowbytes) + (uint32_t)(CB * q) * (SPLIT ? 4u : ESZ),
+                            lhiplane + udh * hibytes + (uint32_t)(CB * q) * 2u);
+                    } else if (LR && udh < (uint32_t)R) {
                         put(lrows, lgbyte + udh * (SPLIT ? lobytes : rowbytes) + (uint32_t)(CB * q) * (SPLIT ? 4u : ESZ),
                             lhiplane + udh * hibytes + (uint32_t)(CB * q) * 2u);
                     } else {
