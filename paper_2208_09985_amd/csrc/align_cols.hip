@@ -345,9 +345,10 @@ __global__ __launch_bounds__(64) void cols_kernel(const AlignArgs a) {
                 const uint32_t tqh = CB * q < 64 ? (uint32_t)(r.thi >> (CB * q)) : 0u;
                 const int ncols = min(max(r.n_w - CB * q, 0), CB);   // this lane's columns inside the text window
                 // match mask of column t: the pattern positions whose base equals text base t,
-                // i.e. plane bits equal to the text bit's in both planes: with m = 0 or ~0 the
-                // text bit, ~((p_lo ^ m_lo) | (p_hi ^ m_hi)); zero past the text window's end,
-                // and set beyond m_w.  Per 32-bit half, one-bit fields sign-extended to masks
+                // i.e. whose bits in both planes equal the text base's.  With m_lo and m_hi all
+                // ones where the text base's low or high plane bit is set (a one-bit field,
+                // sign-extended), that is ~((p_lo ^ m_lo) | (p_hi ^ m_hi)) on each 32-bit half;
+                // zero past the text window's end, and set beyond m_w
                 const uint32_t vmask = ncols >= 32 ? ~0u : (1u << ncols) - 1u;   // ncols <= CB <= 32
                 const uint32_t pl0 = (uint32_t)r.plo, pl1 = (uint32_t)(r.plo >> 32);
                 const uint32_t ph0 = (uint32_t)r.phi, ph1 = (uint32_t)(r.phi >> 32);
