@@ -171,7 +171,11 @@ typedef struct {
                             /* many pairs as 4-window wavefronts one per SIMD hold,    */
                             /* and 16-window wavefronts that fit while leaving at      */
                             /* least 128 SIMDs), -1 = never.  Results are the same     */
-                            /* either way                                              */
+                            /* either way.  A helper that sees no progress of the main */
+                            /* launch for some 55 ms (environment variable             */
+                            /* SCG_HELPER_IDLE_POLLS, read at batch creation, sets the */
+                            /* polls) stops taking pairs; the main launch then keeps   */
+                            /* the pairs it would have handed over                     */
 } scg_params;
 
 typedef struct {
