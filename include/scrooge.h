@@ -135,10 +135,11 @@ typedef struct {
                             /* 8 pairs per CU 4; lengths that vary, longest first      */
                             /* (plain mode, rows in global memory) 4, with just enough */
                             /* wavefronts per CU to keep (all windows / the longest    */
-                            /* pair's windows) windows in flight, when that is fewer   */
-                            /* than the occupancy maximum holds; otherwise 8 (10 when  */
-                            /* those fit one per SIMD and 8 do not); 16 with the       */
-                            /* off-track helpers                                       */
+                            /* pair's windows) windows in flight, when that is at most */
+                            /* one per SIMD, and 16 beside helpers that hold the       */
+                            /* longest pairs when it is more but below the occupancy   */
+                            /* maximum; otherwise 8 (10 when those fit one per SIMD    */
+                            /* and 8 do not); 16 with the off-track helpers            */
     int32_t waves_per_cu;   /* persistent wavefronts per CU (0 = occupancy maximum, or */
                             /* the count the automatic rule for varying lengths picks) */
     int32_t order;          /* SCG_ORDER_* : queue order of pairs                      */
@@ -157,9 +158,9 @@ typedef struct {
                             /* the batch's wavefronts fit one per SIMD (10 windows per */
                             /* wavefront are then picked when 8 would not fit); -1 =   */
                             /* never.  Results are the same either way                 */
-    int32_t offtrack_helpers;  /* column blocks, plain mode, no yields, ablations or    */
-                            /* graph (SCG_FLAG_ROWS_LDS allowed, with 16 windows per   */
-                            /* main wavefront): a pair whose last three                */
+    int32_t offtrack_helpers;  /* column blocks, plain mode, no yields or ablations     */
+                            /* (SCG_FLAG_ROWS_LDS allowed, with 16 windows per main    */
+                            /* wavefront; the graph flag too): a pair whose last three */
                             /* windows each had d_w >= 3(W-O)/5 (it has lost the      */
                             /* diagonal) is handed to a second launch of wavefronts    */
                             /* with 4 windows of 16 lanes each, on the SIMDs the main  */
@@ -171,7 +172,12 @@ typedef struct {
                             /* many pairs as 4-window wavefronts one per SIMD hold,    */
                             /* and 16-window wavefronts that fit while leaving at      */
                             /* least 128 SIMDs), -1 = never.  Results are the same     */
-                            /* either way.  A helper that sees no progress of the main */
+                            /* either way.  Automatic also for lengths that vary, when */
+                            /* the batch needs more than one 4-window wavefront per    */
+                            /* SIMD (W-O at least 30): one helper wavefront per CU     */
+                            /* holds the longest pairs from the start, and 16-window   */
+                            /* wavefronts one per SIMD take the others from the queue. */
+                            /* A helper that sees no progress of the main              */
                             /* launch for some 55 ms (environment variable             */
                             /* SCG_HELPER_IDLE_POLLS, read at batch creation, sets the */
                             /* polls) stops taking pairs; the main launch then keeps   */
@@ -261,7 +267,8 @@ int scg_batch_runs_offsets(const scg_batch* b, int64_t* out);
  * entry bits (32, 48 or 64; 96 or 128 for wide windows; 0 for error-row
  * lanes); out[6] wavefronts of the off-track helper launch (0: none);
  * out[7] its windows per wavefront; out[8] its dynamic LDS bytes per
- * wavefront.  out: 9 int32 in host memory.
+ * wavefront; out[9] the longest pairs it holds from the start (0: only
+ * pairs handed over).  out: 10 int32 in host memory.
  * Errors: SCG_EINVAL. */
 int scg_batch_launch_shape(const scg_batch* b, int32_t* out);
 

@@ -186,11 +186,12 @@ class Batch:
         L.check(rc, "scg_batch_run")
 
     def launch_shape(self) -> dict:
-        out = (ctypes.c_int32 * 9)()
+        out = (ctypes.c_int32 * 10)()
         L.check(self._lib.scg_batch_launch_shape(self.handle, out), "scg_batch_launch_shape")
         kernel = {L.KERNEL_ROWS: "rows", L.KERNEL_COLUMNS: "columns", L.KERNEL_LANES: "lanes", 4: "wide"}[out[0]]
         return {"kernel": kernel, "slots": out[1], "grid": out[2], "lds_bytes": out[3], "one_per_simd": bool(out[4]),
-                "entry_bits": out[5], "helper_grid": out[6], "helper_slots": out[7], "helper_lds_bytes": out[8]}
+                "entry_bits": out[5], "helper_grid": out[6], "helper_slots": out[7], "helper_lds_bytes": out[8],
+                "helper_long_pairs": out[9]}
 
     def stats(self) -> L.Stats:
         st = L.Stats()

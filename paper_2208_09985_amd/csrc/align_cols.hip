@@ -204,13 +204,15 @@ __global__ __launch_bounds__(64) void cols_kernel(const AlignArgs a) {
                     pending = -1;
                     polled = 0;
                     const int pm = a.plen[pid], pn = a.tlen[pid];
-                    if (fresh && (a.bad[pid] || pm == 0)) {
+                    // (a helper sees such pairs only among the long pairs it holds from the start)
+                    if ((fresh || a.helper) && (a.bad[pid] || pm == 0)) {
                         const bool bad = a.bad[pid] != 0;
                         a.edits[pid] = bad ? -1 : 0;
                         a.text_end[pid] = bad ? -1 : 0;
                         a.status[pid] = bad ? 2 : 0;
                         a.n_runs[pid] = 0;
                         atomicAdd(&a.qctl[2], 1u);
+                        if (a.helper) atomicSub(&a.qctl[kQcHInFlight], 1u);
                     } else {
                         pair = pid;
                         m = pm;

@@ -74,6 +74,8 @@ struct scg_batch {
     int dstride = 0;
     int lds_rows = 0;               // column-block kernel: stored rows kept in LDS
     int chain_waves_per_cu = 0;     // column-block kernel: wavefronts per CU for uneven lengths (0: occupancy)
+    int long_k = 0;                 // off-track helpers: the longest pairs they hold from the start
+    int main_grid = 0;              // > 0: the main launch's wavefronts (the rest of the SIMDs are the helpers')
     int help_lds_rows = 0;          // off-track helpers: stored rows kept in LDS, and the LDS bytes they take
     size_t help_lds = 0;
     // off-track helpers: idle polls (each 16 sleeps of 32 x 64 cycles) without a beat of the
@@ -172,12 +174,12 @@ int check_params(const scg_params* p) {
     // global memory, 4, 8 or 10 windows per wavefront
     if (p->one_per_simd < -1 || p->one_per_simd > 1) return SCG_EINVAL;
     if (p->offtrack_helpers < -1 || p->offtrack_helpers > 1) return SCG_EINVAL;
-    // off-track helpers forced: plain mode in the column-block kernel, no yields,
-    // ablations or graph, 8, 10 or 16 windows per main wavefront (16 when the main
-    // launch keeps rows in LDS)
+    // off-track helpers forced: plain mode in the column-block kernel, no yields or
+    // ablations, 8, 10 or 16 windows per main wavefront (16 when the main launch
+    // keeps rows in LDS)
     if (p->offtrack_helpers == 1 &&
         (p->mode != SCG_MODE_PLAIN || p->W > 64 || p->kernel == SCG_KERNEL_ROWS || p->kernel == SCG_KERNEL_LANES ||
-         (p->flags & ~SCG_FLAG_ROWS_LDS) != 0 || p->yield_chars > 0 || p->one_per_simd < 0 ||
+         (p->flags & ~(SCG_FLAG_ROWS_LDS | SCG_FLAG_GRAPH)) != 0 || p->yield_chars > 0 || p->one_per_simd < 0 ||
          (p->slots != 0 && p->slots != 8 && p->slots != 10 && p->slots != 16) ||
          ((p->flags & SCG_FLAG_ROWS_LDS) && p->slots != 0 && p->slots != 16)))
         return SCG_EINVAL;
@@ -233,7 +235,8 @@ int enqueue_run(scg_batch* b, hipStream_t s, int32_t* edits, int32_t* text_end, 
             if (!ev[i]) HIP_TRY(hipEventCreate(&ev[i]));
         HIP_TRY(hipEventRecord(ev[0], s));
     }
-    HIP_TRY(launch_reset(b->qctl_d, b->ring_d, b->qcap, b->order_d, b->stats_d, b->bad_d, b->npairs, s, b->hring_d));
+    HIP_TRY(launch_reset(b->qctl_d, b->ring_d, b->qcap, b->order_d, b->stats_d, b->bad_d, b->npairs, s, b->hring_d,
+                         b->long_k, b->pstate_d));
     int prc = enqueue_pack(b, s);
     if (prc) return prc;
     if (with_events) HIP_TRY(hipEventRecord(ev[1], s));
@@ -725,7 +728,7 @@ int scg_batch_create(scg_ctx* c, const scg_params* params, int32_t npairs, const
         // wavefront (unless slots says otherwise), one wavefront per SIMD.
         {
             const bool rows_lds = (params->flags & SCG_FLAG_ROWS_LDS) != 0;
-            const bool ok = params->mode == SCG_MODE_PLAIN && (params->flags & ~SCG_FLAG_ROWS_LDS) == 0 &&
+            const bool ok = params->mode == SCG_MODE_PLAIN && (params->flags & ~(SCG_FLAG_ROWS_LDS | SCG_FLAG_GRAPH)) == 0 &&
                             params->yield_chars <= 0 && params->one_per_simd >= 0 && params->offtrack_helpers >= 0;
             const int mng = params->slots > 0 ? b->ns : 16;
             const int64_t mwaves = waves(mng);
@@ -760,6 +763,34 @@ int scg_batch_create(scg_ctx* c, const scg_params* params, int32_t npairs, const
                 b->help_lds_rows = std::min(rows, 64);
                 b->help_lds = (size_t)b->help_lds_rows * rowb;
             }
+        }
+        // Lengths that vary, longest first, in a batch too large for the rule above and for
+        // one wavefront per SIMD: the longest pairs' chains of windows set the time, so the
+        // helper launch, one wavefront per CU, holds the longest pairs from the start, and
+        // the main launch runs 16-window wavefronts one per SIMD on the other SIMDs, its
+        // slots taking the other pairs from the queue as they free up; off-track pairs are
+        // handed over as above while helper slots are free.
+        if (b->help_grid == 0 && b->chain_waves_per_cu > kSimdsPerCu && params->mode == SCG_MODE_PLAIN &&
+            (params->flags & ~SCG_FLAG_GRAPH) == 0 &&
+            params->yield_chars <= 0 && params->one_per_simd >= 0 && params->offtrack_helpers >= 0 &&
+            params->W - params->O >= 30 && c->num_cu >= 8) {
+            const int h = c->num_cu;
+            b->ns = 16;
+            b->one = true;
+            b->chain_waves_per_cu = 0;
+            b->help_grid = h;
+            b->main_grid = (int)simds - h;
+            b->long_k = (int)std::min<int64_t>((int64_t)h * kHelperSlots * 3 / 4, npairs / 4);
+            b->mig_k = 3;
+            b->mig_d = std::max(1, 3 * (params->W - params->O) / 5);
+            b->mig_cap = h * kHelperSlots;
+            const int hcap = params->W - params->O;
+            const size_t rowb = (size_t)kHelperSlots * cols_lds_row_bytes(false, hcap, cols_dent_stride(hcap, kHelperSlots));
+            const size_t budget = std::min(c->lds_per_cu / 2, c->lds_per_block);   // at most one helper per CU
+            const size_t reserve = 2048;
+            const int rows = budget > reserve ? (int)((budget - reserve) / rowb) : 0;
+            b->help_lds_rows = std::min(rows, 64);
+            b->help_lds = (size_t)b->help_lds_rows * rowb;
         }
         // SCG_FLAG_ROWS_LDS: the lowest stored rows of each window in LDS, as
         // many as fit while every wavefront the batch needs (or the
@@ -801,6 +832,7 @@ int scg_batch_create(scg_ctx* c, const scg_params* params, int32_t npairs, const
     if (params->waves_per_cu > 0) per_cu = std::min(per_cu, params->waves_per_cu);
     if (b->chain_waves_per_cu > 0) per_cu = std::min(per_cu, b->chain_waves_per_cu);
     b->grid = std::max(1, per_cu * c->num_cu);
+    if (b->main_grid > 0) b->grid = std::min(b->grid, b->main_grid);
     const int64_t need = (npairs + b->ns - 1) / b->ns;   // more wavefronts than slots-worth of pairs idle
     if (b->grid > need) b->grid = (int)std::max<int64_t>(1, need);
     if (b->lanes && npairs > 0) {
@@ -853,6 +885,7 @@ int scg_batch_launch_shape(const scg_batch* b, int32_t* out) {
     out[6] = b->help_grid;
     out[7] = b->help_grid > 0 ? kHelperSlots : 0;
     out[8] = b->help_grid > 0 ? (int32_t)b->help_lds : 0;
+    out[9] = b->long_k;
     if (b->wide) out[5] = cap <= 95 ? 96 : 128;
     else if (b->cols) out[5] = (b->p.flags & SCG_FLAG_STORE_EDGES) || learned ? 64 : (cap <= 31 ? 32 : (cap <= 47 ? 48 : 64));
     else if (b->lanes) out[5] = 64;

@@ -104,9 +104,11 @@ struct AlignArgs {
 };
 
 // launchers (defined in the .hip files)
+// hring (off-track helpers) is cleared, or, with long_k > 0, holds the first long_k pairs of
+// the order from the start (their pstate zeroed) while the main queue starts after them
 hipError_t launch_reset(uint32_t* qctl, int32_t* ring, int64_t qcap, const int32_t* order,
                         unsigned long long* stats, uint8_t* bad, int32_t npairs, hipStream_t s,
-                        int32_t* hring = nullptr);
+                        int32_t* hring = nullptr, int32_t long_k = 0, int32_t* pstate = nullptr);
 hipError_t launch_pack(const uint8_t* seq, const int64_t* off, const int64_t* wordoff, int32_t npairs,
                        int64_t total_words, int64_t total_bytes, Plane2* out, uint8_t* bad, int num_cu, hipStream_t s);
 hipError_t launch_align(const AlignArgs& a, int grid, size_t lds_bytes, hipStream_t s);

@@ -18,19 +18,28 @@ namespace {
 
 __global__ __launch_bounds__(256) void reset_kernel(uint32_t* qctl, int32_t* ring, int64_t qcap,
                                                     const int32_t* order, unsigned long long* stats, uint8_t* bad,
-                                                    int32_t npairs, int32_t* hring) {
+                                                    int32_t npairs, int32_t* hring, int32_t long_k, int32_t* pstate) {
     const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     const int64_t stride = (int64_t)gridDim.x * blockDim.x;
     if (t == 0) {
-        qctl[0] = 0;                 // head
+        qctl[0] = (uint32_t)long_k;  // head: the first long_k pairs of the order go to the helpers
         qctl[1] = (uint32_t)npairs;  // tail: the initial order is already queued
         qctl[2] = 0;                 // pairs finished
-        if (hring) qctl[kQcHHead] = qctl[kQcHTail] = qctl[kQcHInFlight] = qctl[kQcBeat] = 0;   // helper queue, beat
+        if (hring) {
+            // helper queue (holding the long pairs, in flight from the start) and beat
+            qctl[kQcHHead] = 0;
+            qctl[kQcHTail] = qctl[kQcHInFlight] = (uint32_t)long_k;
+            qctl[kQcBeat] = 0;
+        }
     }
     if (t < ST_COUNT) stats[t] = 0;
     for (int64_t x = t; x < npairs; x += stride) bad[x] = 0;
     if (hring)
-        for (int64_t x = t; x < npairs; x += stride) hring[x] = 0;
+        for (int64_t x = t; x < npairs; x += stride) {
+            hring[x] = x < long_k ? order[x] + 1 : 0;
+            if (x < long_k)
+                for (int i = 0; i < 8; ++i) pstate[8 * (int64_t)order[x] + i] = 0;   // a pair from its start
+        }
     for (int64_t x = t; x < qcap; x += stride) ring[x] = x < npairs ? order[x] + 1 : 0;
 }
 
@@ -170,12 +179,14 @@ __global__ __launch_bounds__(256) void pack_short_kernel(const uint8_t* __restri
 }  // namespace
 
 hipError_t launch_reset(uint32_t* qctl, int32_t* ring, int64_t qcap, const int32_t* order,
-                        unsigned long long* stats, uint8_t* bad, int32_t npairs, hipStream_t s, int32_t* hring) {
+                        unsigned long long* stats, uint8_t* bad, int32_t npairs, hipStream_t s, int32_t* hring,
+                        int32_t long_k, int32_t* pstate) {
+    if (long_k > 0 && (!hring || !pstate || long_k > npairs)) return hipErrorInvalidValue;
     int64_t blocks = (qcap + 255) / 256;
     if (blocks < 1) blocks = 1;
     if (blocks > 2048) blocks = 2048;
     hipLaunchKernelGGL(reset_kernel, dim3((unsigned)blocks), dim3(256), 0, s, qctl, ring, qcap, order, stats, bad,
-                       npairs, hring);
+                       npairs, hring, long_k, pstate);
     return hipGetLastError();
 }
 

@@ -289,10 +289,30 @@ def test_offtrack_helpers_stop_waiting(ctx, monkeypatch):
     monkeypatch.delenv("SCG_HELPER_IDLE_POLLS")
 
 
+def test_offtrack_helpers_graph_replays(ctx):
+    # the two launches captured in one hipGraph (the helper stream joins the capture
+    # through the fork and join events): every replay, with eager work between
+    # replays, gives the oracle's results
+    import torch
+    from paper_2208_09985_amd import api
+    b = _offtrack_batch(24, 8, seed=13)
+    ref = oracle.align_batch(b, 64, 24, 64)
+    gb = api.Batch(ctx, b, api.params(kernel="columns", offtrack_helpers=True, graph=True))
+    assert gb.launch_shape()["helper_grid"] > 0
+    for rep in range(3):
+        gb.edits.fill_(-7)
+        gb.n_runs.fill_(0)
+        gb.run()
+        torch.cuda.synchronize()
+        compare(b, gb.result(), ref, f"helpers in a graph, replay {rep}")
+        _ = torch.ones(1000, device=gb.dev).sum().item()
+    gb.close()
+
+
 def test_offtrack_helpers_refused_forms(ctx):
     from paper_2208_09985_amd import _lib as L, api
     b = synth.make_batch("small_100bp", 16)
-    for kw in (dict(mode="fixed", fixed_rows=7), dict(rows_lds=True, slots=10), dict(store_edges=True), dict(graph=True),
+    for kw in (dict(mode="fixed", fixed_rows=7), dict(rows_lds=True, slots=10), dict(store_edges=True),
                dict(slots=4), dict(yield_chars=64), dict(one_per_simd=False), dict(kernel="rows")):
         prm = dict(kernel="columns", offtrack_helpers=True)
         prm.update(kw)

@@ -5,8 +5,9 @@ operation stream (bit-exact).
 * short reads: 100,000 pairs of 250 bp, the default plain launch;
 * long reads: 10,000 pairs of 10 kbp, the default plain launch (the
   benchmark's headline) and, with the committed predictor, learned mode;
-* uneven lengths: 50,000 pairs of log-normal length, the default launch and
-  the launch shape the autotuner picks, replayed from a captured hipGraph;
+* uneven lengths: 50,000 pairs of log-normal length, the default launch (the
+  helpers holding the longest pairs; also with a bad byte in one of them) and the
+  launch shape the autotuner picks, replayed from a captured hipGraph;
 * mixed edit rates: 10,000 pairs of 10 kbp in learned mode with the
   committed predictor, in both kernels.
 """
@@ -96,21 +97,31 @@ def test_uneven_lognormal_all_pairs_autotuned_graph(ctx):
     import torch
     from paper_2208_09985_amd import api, autotune
     w, b, ref = _workload("uneven_lognormal")
-    # the default launch: lengths vary, so pairs go longest first, and the launch keeps
-    # about (all windows / longest chain of windows) in flight in 4-window wavefronts
+    # the default launch: lengths vary, so pairs go longest first; the batch needs more
+    # chains in flight than one wavefront per SIMD holds, so the helper launch (one
+    # wavefront per CU) holds the 768 longest pairs from the start and 16-window
+    # wavefronts one per SIMD take the rest from the queue
     bt = api.Batch(ctx, b, api.params(W=w.W, O=w.O, k=w.k, mode="plain"))
     shape = bt.launch_shape()
     log(f"[full] uneven_lognormal default launch shape {shape}")
-    m = np.diff(b.pat_off)
-    nwin = -(-m // (w.W - w.O))
-    chains = -(-int(nwin.sum()) // int(nwin.max()))
     if ctx.cus == 256:
-        assert shape["kernel"] == "columns" and shape["slots"] == 4 and shape["helper_grid"] == 0, shape
-        assert shape["grid"] == 256 * -(-(-(-chains // 4)) // 256), (shape, chains)
+        assert shape["kernel"] == "columns" and shape["slots"] == 16 and shape["one_per_simd"], shape
+        assert shape["grid"] == 768 and shape["helper_grid"] == 256 and shape["helper_long_pairs"] == 768, shape
     bt.run()
     torch.cuda.synchronize()
     compare(b, bt.result(), ref, "uneven_lognormal full default launch")
     bt.close()
+    # a pair with a non-ACGT byte among the longest ones (held by the helpers) is marked
+    # as bad input, and every other pair keeps its result
+    m = np.diff(b.pat_off)
+    longest = int(np.argmax(m))
+    bb = synth.PairBatch(b.pat.copy(), b.pat_off, b.txt, b.txt_off)
+    bb.pat[int(b.pat_off[longest]) + 5] = ord("N")
+    res = api.align_batch(ctx, bb, W=w.W, O=w.O, k=w.k)
+    assert res.status[longest] == 2 and res.edits[longest] == -1
+    keep = np.arange(b.npairs) != longest
+    assert np.array_equal(res.edits[keep], ref["edits"][keep])
+    assert np.array_equal(res.text_end[keep], ref["text_end"][keep])
     best, trials = autotune.tune(ctx, b, w.W, w.O, w.k, mode="plain", reps=1, cache_path=None, log=log)
     log(f"[full] uneven_lognormal autotuned {best}, graph launch")
     gb = api.Batch(ctx, b, api.params(W=w.W, O=w.O, k=w.k, mode="plain", graph=True, **best))
