@@ -291,7 +291,8 @@ def main():
             entry["learned_row_lanes"]["speedup_vs_headline_kernel"] = round(pms / lms, 3)
         workloads[name] = entry
         del wb
-        # uneven lengths: autotuned launch shape, one hipGraph-captured launch per step
+        # uneven lengths: autotuned launch shape, one hipGraph-captured launch per step (a batch
+        # with off-track helpers is enqueued directly)
         name = "uneven_lognormal"
         log(f"[bench] generating {name}")
         wb = synth.make_batch(name)
@@ -305,7 +306,10 @@ def main():
             e = summary(wb, gms, gst, None if ref is None else same_output(gres, ref[1]),
                         None if ref is None else ref[0])
             e["autotuned"] = best
-            e["graph"] = True
+            gshape = shapes[f"{name} {mode} graph {best}"]
+            # the library enqueues a batch with off-track helpers directly, graph flag or not
+            e["graph"] = gshape["helper_grid"] == 0
+            e["launch"] = gshape
             e["candidates"] = len(trials)
             entry[mode] = e
             if ref is None:

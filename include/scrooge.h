@@ -90,6 +90,9 @@ enum {
 };
 enum {
     SCG_FLAG_GRAPH = 1,              /* replay the batch's launches from a captured hipGraph   */
+                                     /* (ignored when the batch runs off-track helpers: their */
+                                     /* launch runs beside the main one on the context's      */
+                                     /* helper stream, which a graph would not keep)          */
     /* Ablations of the paper's improvements (Section 2.4), plain mode in the column-block     */
     /* kernel only (SCG_EINVAL otherwise); results are unchanged, only the work grows:         */
     SCG_FLAG_NO_EARLY_TERMINATION = 2,  /* every window computes all k_w+1 rows (no ET)        */
@@ -160,7 +163,8 @@ typedef struct {
                             /* never.  Results are the same either way                 */
     int32_t offtrack_helpers;  /* column blocks, plain mode, no yields or ablations     */
                             /* (SCG_FLAG_ROWS_LDS allowed, with 16 windows per main    */
-                            /* wavefront; the graph flag too): a pair whose last three */
+                            /* wavefront; the graph flag too, which is then ignored): */
+                            /* a pair whose last three                                 */
                             /* windows each had d_w >= 3(W-O)/5 (it has lost the      */
                             /* diagonal) is handed to a second launch of wavefronts    */
                             /* with 4 windows of 16 lanes each, on the SIMDs the main  */
@@ -181,7 +185,11 @@ typedef struct {
                             /* launch for some 55 ms (environment variable             */
                             /* SCG_HELPER_IDLE_POLLS, read at batch creation, sets the */
                             /* polls) stops taking pairs; the main launch then keeps   */
-                            /* the pairs it would have handed over                     */
+                            /* the pairs it would have handed over.  The helper launch */
+                            /* runs on one stream per context, created on first use    */
+                            /* and shared by the context's batches: runs of two such   */
+                            /* batches of one context on different streams at once    */
+                            /* are correct, but their helper launches take turns       */
 } scg_params;
 
 typedef struct {

@@ -11,6 +11,7 @@
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
+#include <mutex>
 #include <new>
 #include <numeric>
 #include <vector>
@@ -29,12 +30,18 @@ struct scg_ctx {
     int32_t* budget_d = nullptr;
     uint32_t* operands_d = nullptr; // per-lane MFMA operand blob (64 lanes x 144 B)
     scg_stats last{};               // stats of the last scg_align_batch
+    // the stream of the off-track helper launches, shared by the context's batches and
+    // created once: the runtime spreads streams over a few hardware queues, and a stream
+    // per batch soon lands on the queue of the caller's stream, where the helper launch
+    // then waits for the main launch to finish instead of running beside it
+    hipStream_t help_stream = nullptr;
+    std::mutex help_mu;
 };
 
 struct scg_batch {
     scg_ctx* ctx = nullptr;
     bool one = false;   // column blocks: one wavefront per SIMD
-    // off-track helpers: a second launch of 4-window wavefronts on its own stream
+    // off-track helpers: a second launch of 4-window wavefronts on the context's helper stream
     int help_grid = 0;
     uint64_t* help_dent_d = nullptr;
     int32_t* hring_d = nullptr;
@@ -119,6 +126,20 @@ int from_hip(hipError_t e, const char* what = "HIP call") {
         if (_e != hipSuccess) return from_hip(_e, #x);   \
     } while (0)
 
+// the context's helper stream, created on first use (the device is current)
+int ctx_helper_stream(scg_ctx* c, hipStream_t* out) {
+    std::lock_guard<std::mutex> lock(c->help_mu);
+    if (!c->help_stream) {
+        const int rc = from_hip(hipStreamCreateWithFlags(&c->help_stream, hipStreamNonBlocking), "helper stream");
+        if (rc) {
+            c->help_stream = nullptr;
+            return rc;
+        }
+    }
+    *out = c->help_stream;
+    return SCG_OK;
+}
+
 template <class T>
 int dev_alloc(T** p, size_t count) {
     *p = nullptr;
@@ -199,7 +220,6 @@ void free_batch(scg_batch* b) {
             if (e) (void)hipEventDestroy(e);
     if (b->fork_ev) (void)hipEventDestroy(b->fork_ev);
     if (b->join_ev) (void)hipEventDestroy(b->join_ev);
-    if (b->s2) (void)hipStreamDestroy(b->s2);
     void* ptrs[] = {b->own_seq ? b->pat_d : nullptr, b->own_seq ? b->txt_d : nullptr, b->pat_off_d, b->txt_off_d,
                     b->pplanes, b->tplanes, b->pword_d, b->tword_d, b->plen_d, b->tlen_d, b->bad_d, b->order_d,
                     b->runs_off_d, b->qctl_d, b->ring_d, b->pstate_d, b->stats_d, b->dent_d, b->pin_d, b->tin_d,
@@ -433,6 +453,10 @@ int scg_create(scg_ctx** out, int device, const char* weights_path) {
 
 void scg_destroy(scg_ctx* c) {
     if (!c) return;
+    if (c->help_stream) {
+        (void)hipSetDevice(c->device);
+        (void)hipStreamDestroy(c->help_stream);
+    }
     if (c->model_d) (void)hipFree(c->model_d);
     if (c->budget_d) (void)hipFree(c->budget_d);
     if (c->operands_d) (void)hipFree(c->operands_d);
@@ -857,7 +881,7 @@ int scg_batch_create(scg_ctx* c, const scg_params* params, int32_t npairs, const
         const int cap = params->W - params->O;
         if ((rc = dev_alloc(&b->help_dent_d, cols_dent_bytes(b->help_grid, cap, kHelperSlots, false, 0) / sizeof(uint64_t))) ||
             (rc = dev_alloc(&b->hring_d, (size_t)npairs)) ||
-            (rc = from_hip(hipStreamCreateWithFlags(&b->s2, hipStreamNonBlocking))) ||
+            (rc = ctx_helper_stream(b->ctx, &b->s2)) ||
             (rc = from_hip(hipEventCreateWithFlags(&b->fork_ev, hipEventDisableTiming))) ||
             (rc = from_hip(hipEventCreateWithFlags(&b->join_ev, hipEventDisableTiming))))
             return fail(rc);
@@ -905,7 +929,12 @@ int scg_batch_run(scg_batch* b, void* stream, int32_t* edits, int32_t* text_end,
     if (b->npairs > 0 && (!edits || !text_end || !status || !runs || !n_runs)) return SCG_EINVAL;
     HIP_TRY(hipSetDevice(b->ctx->device));
     hipStream_t s = (hipStream_t)stream;
-    if (!(b->p.flags & SCG_FLAG_GRAPH)) {
+    // with the off-track helpers the launches are enqueued directly even under the graph
+    // flag: a captured graph runs the helper branch on a stream the runtime picks, which
+    // can share the main launch's hardware queue (the helpers then start late or only
+    // after the main launch), and these batches run for milliseconds, so the launch
+    // calls a graph saves do not matter
+    if (!(b->p.flags & SCG_FLAG_GRAPH) || b->help_grid > 0) {
         b->timed = true;
         return enqueue_run(b, s, edits, text_end, status, runs, n_runs, true);
     }

@@ -290,9 +290,9 @@ def test_offtrack_helpers_stop_waiting(ctx, monkeypatch):
 
 
 def test_offtrack_helpers_graph_replays(ctx):
-    # the two launches captured in one hipGraph (the helper stream joins the capture
-    # through the fork and join events): every replay, with eager work between
-    # replays, gives the oracle's results
+    # the graph flag on a batch with helpers: the launches are enqueued directly (the
+    # helper launch must run beside the main one on the context's helper stream); every
+    # run, with eager work between runs, gives the oracle's results
     import torch
     from paper_2208_09985_amd import api
     b = _offtrack_batch(24, 8, seed=13)
@@ -304,7 +304,7 @@ def test_offtrack_helpers_graph_replays(ctx):
         gb.n_runs.fill_(0)
         gb.run()
         torch.cuda.synchronize()
-        compare(b, gb.result(), ref, f"helpers in a graph, replay {rep}")
+        compare(b, gb.result(), ref, f"helpers with the graph flag, run {rep}")
         _ = torch.ones(1000, device=gb.dev).sum().item()
     gb.close()
 
