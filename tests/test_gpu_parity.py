@@ -309,6 +309,31 @@ def test_offtrack_helpers_graph_replays(ctx):
     gb.close()
 
 
+def test_offtrack_helpers_two_batches_two_streams(ctx):
+    # two batches of one context share the context's helper stream: run at once on two
+    # streams (their helper launches take turns), both give the oracle's results, twice
+    import torch
+    from paper_2208_09985_amd import api
+    b1 = _offtrack_batch(24, 8, seed=21)
+    b2 = _offtrack_batch(16, 10, seed=22)
+    ref1 = oracle.align_batch(b1, 64, 24, 64)
+    ref2 = oracle.align_batch(b2, 64, 24, 64)
+    g1 = api.Batch(ctx, b1, api.params(kernel="columns", offtrack_helpers=True))
+    g2 = api.Batch(ctx, b2, api.params(kernel="columns", offtrack_helpers=True))
+    assert g1.launch_shape()["helper_grid"] > 0 and g2.launch_shape()["helper_grid"] > 0
+    s1, s2 = torch.cuda.Stream(), torch.cuda.Stream()
+    torch.cuda.synchronize()
+    for rep in range(2):
+        log(f"[parity] two helper batches on two streams, run {rep}")
+        g1.run(s1)
+        g2.run(s2)
+        torch.cuda.synchronize()
+        compare(b1, g1.result(), ref1, f"first of two batches on two streams, run {rep}")
+        compare(b2, g2.result(), ref2, f"second of two batches on two streams, run {rep}")
+    g1.close()
+    g2.close()
+
+
 def test_offtrack_helpers_refused_forms(ctx):
     from paper_2208_09985_amd import _lib as L, api
     b = synth.make_batch("small_100bp", 16)
