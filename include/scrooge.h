@@ -232,6 +232,8 @@ void scg_params_default(scg_params* p);
  * w2[H*C], b2[C] (as scg_set_model), nothing after.
  * Errors: SCG_EINVAL (also a missing or malformed file), SCG_EDEVICE. */
 int scg_create(scg_ctx** out, int device, const char* weights_path);
+/* Release the context and its helper stream: destroy its batches first, once
+ * their runs have finished. */
 void scg_destroy(scg_ctx* ctx);
 
 /* Number of compute units of the context's device (for launch planning). */
