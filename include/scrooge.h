@@ -189,7 +189,10 @@ typedef struct {
                             /* runs on one stream per context, created on first use    */
                             /* and shared by the context's batches: runs of two such   */
                             /* batches of one context on different streams at once    */
-                            /* are correct, but their helper launches take turns       */
+                            /* are correct, but their helper launches take turns; a    */
+                            /* caller that captures such a run into a graph of its own */
+                            /* captures the helper stream with it, so no other batch  */
+                            /* of the context may run until the capture ends           */
 } scg_params;
 
 typedef struct {
